@@ -147,6 +147,9 @@ def _term_params(spec: SeriesSpec, p: int, kidx: torch.Tensor, device):
         ph = _key(spec.seed, 0x31, p, j, kidx) & (Q - 1)
         freqs.append(f)
         phases.append(ph)
+    if not freqs:
+        empty = torch.empty((0, kidx.numel()), dtype=torch.int64, device=device)
+        return empty, empty
     return torch.stack(freqs), torch.stack(phases)
 
 
