@@ -1,0 +1,200 @@
+/*
+ * tacaw.h -- C ABI of the TACAW spectral hot path on MI355X (gfx950).
+ *
+ * The library reduces, for every probe position, a time series of exit waves
+ * psi(k, t) to the ultra-low-loss spectrum S(k, omega) and its detector
+ * integrals (paper: Sec. I Eq. 1 for |FT_t psi|^2; Sec. II.B.2 for the Welch
+ * chunking "s_{n+1} = s_n + L/nu" and the window; Eq. 2 for the chunk average
+ * united over scan batches; the DetectorSet paragraphs of Sec. II.B.1 and
+ * App. B for mask integration).
+ *
+ * Conventions shared by every entry point:
+ *  - Pixels k run over a ny x nx reciprocal-space grid, row-major, contiguous.
+ *  - Frequency bins are in FFT order: bin m holds nu_m = m / (L dt) for
+ *    m < L/2 and (m - L) / (L dt) otherwise; the forward kernel is
+ *    exp(-2 pi i m t / L) (Sec. III.B transform sign), so exp(+2 pi i nu t)
+ *    lands at +nu.
+ *  - All device pointers are caller-owned HIP device memory (e.g. torch
+ *    tensors) unless stated otherwise. Work is enqueued on the plan's HIP
+ *    stream in call order; an input buffer must stay alive until the stream has
+ *    passed the call that reads it. Calls return after enqueueing.
+ *  - Return value: 0 (TACAW_OK) or a negative TACAW_ERR_* code; no exception
+ *    crosses the ABI. tacaw_last_error() gives a thread-local message.
+ *    Argument, shape and state checks run on the host before any HIP call.
+ *  - A plan is not thread-safe; distinct plans may run on distinct streams.
+ */
+#ifndef TACAW_H
+#define TACAW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------- */
+#define TACAW_OK 0
+#define TACAW_ERR_INVALID_ARG (-1) /* bad value, null pointer, misaligned pointer */
+#define TACAW_ERR_SHAPE (-2)       /* sizes inconsistent with the plan            */
+#define TACAW_ERR_STATE (-3)       /* call not allowed in the plan's state         */
+#define TACAW_ERR_OOM (-4)         /* device allocation failed or size too large   */
+#define TACAW_ERR_HIP (-5)         /* a HIP runtime call failed                    */
+#define TACAW_ERR_UNSUPPORTED (-6) /* valid but not implemented combination        */
+
+/* ---- window w(t), t = 0..L-1 (Sec. II.B.2; Sec. III.A) ------------------ */
+#define TACAW_WIN_HANN 0       /* periodic Hann 1/2 - 1/2 cos(2 pi t / L) (default)   */
+#define TACAW_WIN_RECT 1       /* no window (all ones)                                */
+#define TACAW_WIN_HANN_WIDTH 2 /* width-r Hann: 1/2 + 1/2 cos(2 pi (t - L/2)/(r L))    */
+                               /* for |t - L/2| <= r L / 2, else 0; r = window_param  */
+#define TACAW_WIN_TUKEY 3      /* periodic Tukey, window_param = alpha (taper share)  */
+
+/* ---- elastic-mean handling (the mean is removed before the window) ------ */
+#define TACAW_MEAN_GLOBAL 0      /* mean over the frames that enter a chunk (default) */
+#define TACAW_MEAN_PER_SEGMENT 1 /* mean of each chunk (reserved: UNSUPPORTED)        */
+#define TACAW_MEAN_NONE 2        /* keep the zero-loss peak (the paper's behaviour)   */
+
+/* ---- time transform ------------------------------------------------------ */
+#define TACAW_FFT_F32 0     /* radix FFT in FP32, staged in LDS                      */
+#define TACAW_GEMM_BF16X3 1 /* DFT as a GEMM on MFMA, bf16 hi/lo split x3, FP32 acc   */
+#define TACAW_GEMM_F16X3 2  /* DFT as a GEMM on MFMA, scaled fp16 hi/lo split x3     */
+
+/* ---- input element type -------------------------------------------------- */
+#define TACAW_C64 0  /* complex64: interleaved float (re, im), 8 bytes           */
+#define TACAW_C128 1 /* complex128: interleaved double (re, im), 16 bytes        */
+
+/* ---- reduction over probes (Eq. 2: union of scan batches) --------------- */
+#define TACAW_PROBE_MEAN 0 /* S = average over probes (default)                 */
+#define TACAW_PROBE_SUM 1  /* S = sum over probes                                */
+
+typedef struct tacaw_plan_s* tacaw_plan_t;
+
+/* Plan descriptor. Chunk (segment) s covers frames [s*hop, s*hop + seg_len);
+ * only full chunks are used: N_s = (n_frames - seg_len) / hop + 1, and frames
+ * at or beyond (N_s - 1) * hop + seg_len are accepted and ignored. */
+typedef struct {
+  int32_t n_probe;        /* probes (scan positions) in this plan, >= 1              */
+  int32_t ny, nx;         /* reciprocal-space grid, ny * nx pixels                   */
+  int64_t n_frames;       /* frames that will be pushed per probe (N_t >= seg_len)   */
+  int32_t seg_len;        /* L: power of two, 64 <= L <= 1024                        */
+  int32_t hop;            /* H = L / nu with integer division, 1 <= H <= L           */
+  int32_t window;         /* TACAW_WIN_*                                             */
+  double window_param;    /* r for HANN_WIDTH (> 0), alpha for TUKEY ([0, 1])        */
+  int32_t mean_mode;      /* TACAW_MEAN_*                                            */
+  int32_t transform;      /* TACAW_FFT_F32 or TACAW_GEMM_*                           */
+  int32_t in_dtype;       /* TACAW_C64 or TACAW_C128                                 */
+  int32_t probe_reduce;   /* TACAW_PROBE_MEAN or TACAW_PROBE_SUM                     */
+  double dt_fs;           /* frame interval in fs (> 0; axis helpers only)           */
+  int32_t n_det;          /* detector masks given at plan time (0..8)                */
+  const double* d_masks;  /* device [n_det][ny][nx] float64 weights, or NULL if      */
+                          /* n_det == 0; copied into the plan. Needed for per-probe  */
+                          /* detector spectra (STEM images), which are fused into    */
+                          /* the push.                                               */
+  int32_t max_probes_in_flight; /* probes with a partially pushed series at once    */
+                                /* (streaming ring capacity); 0 = n_probe            */
+  int32_t flags;          /* TACAW_FLAG_* bits                                       */
+} tacaw_plan_desc;
+
+/* flags: record HIP events around the chunk kernel of every push; the last
+ * duration is reported in tacaw_plan_info.last_chunk_kernel_ms (reading it
+ * synchronizes with the plan's stream). */
+#define TACAW_FLAG_TIME_KERNELS 1
+
+typedef struct {
+  int32_t n_segments;     /* N_s                                                     */
+  int32_t n_omega;        /* frequency bins (= seg_len)                              */
+  int64_t frames_used;    /* (N_s - 1) * hop + seg_len                               */
+  int64_t frames_dropped; /* frames pushed so far beyond frames_used (all probes)    */
+  int64_t device_bytes;   /* device memory currently owned by the plan               */
+  int32_t state;          /* 0 open, 1 finalized                                     */
+  int32_t probes_complete;/* probes whose whole series has been pushed               */
+  double window_sum_sq;   /* sum_t w(t)^2                                            */
+  int32_t tile_pixels;    /* pixels per workgroup tile of the push kernel            */
+  int32_t reserved;
+  double last_chunk_kernel_ms; /* duration of the last push's chunk kernel (flag set) */
+} tacaw_plan_info;
+
+/* Create a plan: validates desc on the host (no HIP call on failure), then
+ * allocates the plan's FP64 accumulators on the current HIP device and records
+ * hip_stream (a hipStream_t; NULL = default stream) for all later work.
+ * Errors: INVALID_ARG, UNSUPPORTED, OOM, HIP. *out is NULL on error. */
+int tacaw_plan(const tacaw_plan_desc* desc, void* hip_stream, tacaw_plan_t* out);
+
+/* Host-only validation of a descriptor (the checks tacaw_plan runs first). */
+int tacaw_plan_check(const tacaw_plan_desc* desc);
+
+/* Push the next n_frames frames of probes [probe0, probe0 + n_probes) in time
+ * order (Sec. II.B: exit waves are processed on the fly as they are produced).
+ * Element (i, n, k) of the push, for probe probe0 + i, frame cursor + n and
+ * pixel k, is at d_frames + i * probe_stride + n * frame_stride + k, strides in
+ * ELEMENTS of in_dtype (pixels contiguous). All probes of one push must have
+ * received the same number of frames before. Every chunk completed by this push
+ * is windowed, transformed, squared and accumulated in FP64; frames that later
+ * chunks still need are copied into a plan-owned ring (last L frames per probe
+ * in flight), so a series may arrive in any number of pieces. The result does
+ * not depend on how frames or probes are split into pushes (App. B: batch shape
+ * does not influence the results).
+ * Errors: INVALID_ARG (null/misaligned pointer, bad stride), SHAPE (probe range
+ * or frame count beyond the plan), STATE (plan finalized, probes at different
+ * frame cursors, ring capacity exceeded), OOM, HIP. */
+int tacaw_push_frames(tacaw_plan_t plan, const void* d_frames, int32_t probe0, int32_t n_probes,
+                      int64_t n_frames, int64_t probe_stride, int64_t frame_stride);
+
+/* Finish the reduction once every probe's series has been pushed: applies the
+ * exact elastic-mean correction, normalises per voxel by 1 / (L sum_t w^2) and
+ * averages over chunks (and probes, Eq. 2). Writes S(m, k) as float64
+ * [n_omega][ny][nx] to d_S when d_S is not NULL (caller-owned device buffer);
+ * the plan keeps its own copy for tacaw_detector_spectra and tacaw_backward.
+ * Errors: STATE (already finalized, or a probe's series incomplete), HIP. */
+int tacaw_finalize(tacaw_plan_t plan, double* d_S);
+
+/* Detector (energy-filtered) spectra from a finalized plan:
+ * D_j(m) = sum_k M_j(k) S(m, k) into d_D [n_det][n_omega] (float64, device).
+ * d_masks_or_null: device [n_det][ny][nx] float64 masks, or NULL to use the
+ * plan's masks (then n_det must equal the plan's). d_Dp_or_null: device
+ * [n_det][n_probe][n_omega] float64 per-probe spectra (one STEM-EELS image per
+ * detector and bin); requires the plan's own masks.
+ * Errors: STATE (not finalized), INVALID_ARG, HIP. */
+int tacaw_detector_spectra(tacaw_plan_t plan, const double* d_masks_or_null, int32_t n_det,
+                           double* d_D, double* d_Dp_or_null);
+
+/* Adjoint of the finalized plan's outputs with respect to the input series and
+ * the window parameter. Upstream gradients (any may be NULL, all device
+ * float64): d_gS [n_omega][ny][nx] (dLoss/dS), d_gD [n_det][n_omega]
+ * (dLoss/dD_j, plan masks), d_gDp [n_det][n_probe][n_omega] (dLoss/dD_{j,p}).
+ * d_frames: the complete series of probes [probe0, probe0 + n_probes) again
+ * (same layout rules as tacaw_push_frames, all frames_used frames present);
+ * chunk transforms are recomputed, not stored. d_grad_frames: output, same
+ * dtype and strides as d_frames, d/dRe + i d/dIm convention; it is fully
+ * written for frames < frames_used and left untouched beyond. d_grad_wparam:
+ * device float64 scalar that receives (+=) dLoss/d(window_param) for
+ * HANN_WIDTH plans (may be NULL). Mean modes GLOBAL and NONE.
+ * Errors: STATE (not finalized), INVALID_ARG, UNSUPPORTED, HIP. */
+int tacaw_backward(tacaw_plan_t plan, const void* d_frames, int32_t probe0, int32_t n_probes,
+                   int64_t probe_stride, int64_t frame_stride, const double* d_gS,
+                   const double* d_gD, const double* d_gDp, void* d_grad_frames,
+                   double* d_grad_wparam);
+
+/* Zero every accumulator and frame cursor so the plan can take a new series of
+ * the same shape (buffers are kept). */
+int tacaw_reset(tacaw_plan_t plan);
+
+/* Replace the stream used for subsequent calls. */
+int tacaw_set_stream(tacaw_plan_t plan, void* hip_stream);
+
+/* Sizes and counters of a plan (host call, no device work). */
+int tacaw_plan_get_info(tacaw_plan_t plan, tacaw_plan_info* info);
+
+/* Free every plan-owned device buffer (waits for the plan's stream). */
+void tacaw_destroy(tacaw_plan_t plan);
+
+/* Message of the last error on this thread ("" if none). */
+const char* tacaw_last_error(void);
+
+/* Library version string. */
+const char* tacaw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TACAW_H */

@@ -1,0 +1,334 @@
+// Auxiliary kernels of the plan: zero fills, per-probe references, the exact
+// FP64 mean pre-pass, ring stores for streamed series, per-probe detector
+// partial reduction, the exact elastic-mean correction, normalisation and the
+// masked detector reduction D_j(m) = sum_k M_j(k) S(m, k) (DetectorSet,
+// Sec. II.B.1 of the paper).
+#include "tacaw_internal.h"
+
+namespace tacaw {
+
+static inline int blocks_for(int64_t n, int bs, int cap = 65535 * 8) {
+  int64_t b = (n + bs - 1) / bs;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+__global__ void fill_zero_kernel(uint4* p, int64_t n16, unsigned char* tail, int ntail) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+  if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st) {
+  if (bytes <= 0) return hipSuccess;
+  const int64_t n16 = bytes / 16;
+  const int ntail = (int)(bytes - n16 * 16);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks_for(n16, 256, 8192)), dim3(256), 0, st,
+                     (uint4*)p, n16, (unsigned char*)p + n16 * 16, ntail);
+  return hipGetLastError();
+}
+
+template <typename InT>
+__global__ void ref_first_kernel(const InT* in, int64_t pstride, int32_t probe0, int32_t n_probes,
+                                 int32_t n_k, double2* cref) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (k >= n_k || i >= n_probes) return;
+  const InT v = in[(int64_t)i * pstride + k];
+  cref[(int64_t)(probe0 + i) * n_k + k] = make_double2((double)v.x, (double)v.y);
+}
+
+hipError_t launch_ref_first_frame(const void* in, int in_dtype, int64_t pstride, int32_t probe0,
+                                  int32_t n_probes, int32_t n_k, double2* cref, hipStream_t st) {
+  dim3 g((n_k + 255) / 256, n_probes);
+  if (in_dtype == 1)
+    hipLaunchKernelGGL(ref_first_kernel<double2>, g, dim3(256), 0, st, (const double2*)in,
+                       pstride, probe0, n_probes, n_k, cref);
+  else
+    hipLaunchKernelGGL(ref_first_kernel<float2>, g, dim3(256), 0, st, (const float2*)in, pstride,
+                       probe0, n_probes, n_k, cref);
+  return hipGetLastError();
+}
+
+// Exact FP64 time mean over frames [0, n_used) of each (probe, pixel).
+template <typename InT>
+__global__ void mean_kernel(const InT* in, int64_t pstride, int64_t fstride, int64_t n_used,
+                            int32_t probe0, int32_t n_probes, int32_t n_k, double2* out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (k >= n_k || i >= n_probes) return;
+  const InT* p = in + (int64_t)i * pstride + k;
+  double sx = 0.0, sy = 0.0;
+  for (int64_t n = 0; n < n_used; ++n) {
+    const InT v = p[n * fstride];
+    sx += (double)v.x;
+    sy += (double)v.y;
+  }
+  out[(int64_t)(probe0 + i) * n_k + k] = make_double2(sx / (double)n_used, sy / (double)n_used);
+}
+
+hipError_t launch_mean_exact(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
+                             int64_t n_used, int32_t probe0, int32_t n_probes, int32_t n_k,
+                             double2* mu, hipStream_t st) {
+  dim3 g((n_k + 255) / 256, n_probes);
+  if (in_dtype == 1)
+    hipLaunchKernelGGL(mean_kernel<double2>, g, dim3(256), 0, st, (const double2*)in, pstride,
+                       fstride, n_used, probe0, n_probes, n_k, mu);
+  else
+    hipLaunchKernelGGL(mean_kernel<float2>, g, dim3(256), 0, st, (const float2*)in, pstride,
+                       fstride, n_used, probe0, n_probes, n_k, mu);
+  return hipGetLastError();
+}
+
+hipError_t launch_ref_mean(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
+                           int64_t n_used, int32_t probe0, int32_t n_probes, int32_t n_k,
+                           double2* cref, hipStream_t st) {
+  return launch_mean_exact(in, in_dtype, pstride, fstride, n_used, probe0, n_probes, n_k, cref,
+                           st);
+}
+
+// ring[slot][f % L][k] = in[i][f - push_begin][k] for f in [f_lo, f_hi)
+template <typename InT>
+__global__ void ring_store_kernel(const InT* in, int64_t pstride, int64_t fstride,
+                                  int64_t push_begin, int64_t f_lo, int32_t n_f, int32_t probe0,
+                                  int32_t n_slots, int32_t L, int32_t n_k, InT* ring) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int fi = blockIdx.y;
+  const int i = blockIdx.z;
+  if (k >= n_k || fi >= n_f) return;
+  const int64_t f = f_lo + fi;
+  const int slot = (probe0 + i) % n_slots;
+  ring[((int64_t)slot * L + (f % L)) * n_k + k] = in[(int64_t)i * pstride + (f - push_begin) * fstride + k];
+}
+
+hipError_t launch_ring_store(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
+                             int64_t push_begin, int64_t f_lo, int64_t f_hi, int32_t probe0,
+                             int32_t n_probes, int32_t n_slots, int32_t L, int32_t n_k, void* ring,
+                             hipStream_t st) {
+  const int64_t nf = f_hi - f_lo;
+  if (nf <= 0) return hipSuccess;
+  dim3 g((n_k + 255) / 256, (unsigned)nf, n_probes);
+  if (in_dtype == 1)
+    hipLaunchKernelGGL(ring_store_kernel<double2>, g, dim3(256), 0, st, (const double2*)in,
+                       pstride, fstride, push_begin, f_lo, (int32_t)nf, probe0, n_slots, L, n_k,
+                       (double2*)ring);
+  else
+    hipLaunchKernelGGL(ring_store_kernel<float2>, g, dim3(256), 0, st, (const float2*)in, pstride,
+                       fstride, push_begin, f_lo, (int32_t)nf, probe0, n_slots, L, n_k,
+                       (float2*)ring);
+  return hipGetLastError();
+}
+
+// Dp[d][probe0 + i][m] += sum_slot (part[slot][i][d][m] - part[slot][i-1][d][m]); the
+// partials hold cumulative sums over the launch's probes 0..i.
+__global__ void dpart_reduce_kernel(const double* part, int32_t n_active, int32_t n_probes,
+                                    int32_t n_det, int32_t L, int32_t probe0, int32_t n_probe_total,
+                                    double* Dp) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int d = blockIdx.y;
+  const int i = blockIdx.z;
+  if (m >= L) return;
+  const int64_t per_slot = (int64_t)n_probes * n_det * L;
+  double cur = 0.0, prev = 0.0;
+  for (int s = 0; s < n_active; ++s) {
+    const double* base = part + s * per_slot + (int64_t)d * L + m;
+    cur += base[(int64_t)i * n_det * L];
+    if (i > 0) prev += base[(int64_t)(i - 1) * n_det * L];
+  }
+  Dp[((int64_t)d * n_probe_total + probe0 + i) * L + m] += cur - prev;
+}
+
+hipError_t launch_dpart_reduce(const double* dpart, int32_t n_active, int32_t n_probes,
+                               int32_t n_det, int32_t L, int32_t probe0, int32_t n_probe_total,
+                               double* Dp, hipStream_t st) {
+  dim3 g((L + 127) / 128, n_det, n_probes);
+  hipLaunchKernelGGL(dpart_reduce_kernel, g, dim3(128), 0, st, dpart, n_active, n_probes, n_det,
+                     L, probe0, n_probe_total, Dp);
+  return hipGetLastError();
+}
+
+// ---- exact elastic-mean correction -----------------------------------------
+// For chunk spectra of the reference-subtracted series X'_s and the true
+// mean-subtracted X_s = X'_s - delta W (delta = mu - c):
+//   sum_s |X_s|^2 = sum_s |X'_s|^2 - 2 Re(conj(delta W) sum_s X'_s) + N_s |delta W|^2
+__device__ __forceinline__ double corr_term(const CorrArgs& c, int p, int64_t k, int b) {
+  const double2 cr = c.cref[(int64_t)p * c.n_k + k];
+  double2 delta;
+  if (c.mean_global) {
+    const double2 ms = c.msum[(int64_t)p * c.n_k + k];
+    delta = make_double2(ms.x * c.inv_nused, ms.y * c.inv_nused);
+  } else {
+    delta = make_double2(-cr.x, -cr.y);
+  }
+  const double2 w = c.wbin[b];
+  const double2 dw = make_double2(delta.x * w.x - delta.y * w.y, delta.x * w.y + delta.y * w.x);
+  const double2 xs = c.xs[((int64_t)p * kMaxCorr + b) * c.n_k + k];
+  // Re(conj(dw) * xs) = dw.x xs.x + dw.y xs.y
+  return -2.0 * (dw.x * xs.x + dw.y * xs.y) + c.n_seg * (dw.x * dw.x + dw.y * dw.y);
+}
+
+__global__ void correct_S_kernel(const CorrArgs c, double* S) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= c.n_k) return;
+  for (int b = 0; b < c.n_corr; ++b) {
+    double sum = 0.0;
+    for (int p = 0; p < c.n_probe; ++p) sum += corr_term(c, p, k, b);
+    S[(int64_t)c.bins[b] * c.n_k + k] += sum;
+  }
+}
+
+hipError_t launch_correct_S(const CorrArgs& c, double* S, double* /*out*/, double /*kappa*/,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(correct_S_kernel, dim3((c.n_k + 255) / 256), dim3(256), 0, st, c, S);
+  return hipGetLastError();
+}
+
+// Dp[d][p][bin_b] += sum_k M_d(k) corr_p(b, k)
+__global__ void correct_Dp_kernel(const CorrArgs c, const double* masks, int32_t n_det,
+                                  double* Dp) {
+  const int p = blockIdx.y;
+  __shared__ double red[256];
+  double accd[kMaxDet * kMaxCorr];
+#pragma unroll
+  for (int i = 0; i < kMaxDet * kMaxCorr; ++i) accd[i] = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < c.n_k;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    double ct[kMaxCorr];
+#pragma unroll
+    for (int b = 0; b < kMaxCorr; ++b) ct[b] = (b < c.n_corr) ? corr_term(c, p, k, b) : 0.0;
+#pragma unroll
+    for (int d = 0; d < kMaxDet; ++d) {
+      if (d < n_det) {
+        const double m = masks[(int64_t)d * c.n_k + k];
+#pragma unroll
+        for (int b = 0; b < kMaxCorr; ++b) accd[d * kMaxCorr + b] += m * ct[b];
+      }
+    }
+  }
+  for (int d = 0; d < n_det; ++d) {
+    for (int b = 0; b < c.n_corr; ++b) {
+      red[threadIdx.x] = accd[d * kMaxCorr + b];
+      __syncthreads();
+      for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0)
+        atomicAdd(&Dp[((int64_t)d * c.n_probe + p) * c.L + c.bins[b]], red[0]);
+      __syncthreads();
+    }
+  }
+}
+
+hipError_t launch_correct_Dp(const CorrArgs& c, const double* masks, int32_t n_det, double* Dp,
+                             hipStream_t st) {
+  const int gx = (int)((c.n_k + 256 * 16 - 1) / (256 * 16));
+  hipLaunchKernelGGL(correct_Dp_kernel, dim3(gx > 0 ? gx : 1, c.n_probe), dim3(256), 0, st, c,
+                     masks, n_det, Dp);
+  return hipGetLastError();
+}
+
+// out = in * kappa (in place when out == in)
+__global__ void scale_copy_kernel(double* S, double* out, int64_t n, double kappa) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double v = S[i] * kappa;
+    S[i] = v;
+    if (out) out[i] = v;
+  }
+}
+
+hipError_t launch_finalize_S(double* S, double* out, int64_t n_elem, double kappa,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(scale_copy_kernel, dim3(blocks_for(n_elem, 256, 8192)), dim3(256), 0, st, S,
+                     out, n_elem, kappa);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(double* p, int64_t n, double k, hipStream_t st) {
+  return launch_finalize_S(p, nullptr, n, k, st);
+}
+
+// D[d][m] += sum over a pixel chunk of M_d(k) S(m, k); 8 bins per block.
+constexpr int kDetBins = 8;
+__global__ void detector_kernel(const double* S, const double* masks, int32_t n_det, int32_t L,
+                                int32_t n_k, int32_t chunk, double* D) {
+  const int m0 = blockIdx.y * kDetBins;
+  const int64_t k0 = (int64_t)blockIdx.x * chunk;
+  const int64_t k1 = (k0 + chunk < n_k) ? k0 + chunk : n_k;
+  double acc[kDetBins][kMaxDet];
+#pragma unroll
+  for (int b = 0; b < kDetBins; ++b)
+#pragma unroll
+    for (int d = 0; d < kMaxDet; ++d) acc[b][d] = 0.0;
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
+    double mk[kMaxDet];
+#pragma unroll
+    for (int d = 0; d < kMaxDet; ++d) mk[d] = (d < n_det) ? masks[(int64_t)d * n_k + k] : 0.0;
+#pragma unroll
+    for (int b = 0; b < kDetBins; ++b) {
+      if (m0 + b < L) {
+        const double s = S[(int64_t)(m0 + b) * n_k + k];
+#pragma unroll
+        for (int d = 0; d < kMaxDet; ++d) acc[b][d] += mk[d] * s;
+      }
+    }
+  }
+  __shared__ double red[256];
+  for (int b = 0; b < kDetBins; ++b) {
+    for (int d = 0; d < n_det; ++d) {
+      double v = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < kDetBins; ++bb)
+#pragma unroll
+        for (int dd = 0; dd < kMaxDet; ++dd)
+          if (bb == b && dd == d) v = acc[bb][dd];
+      red[threadIdx.x] = v;
+      __syncthreads();
+      for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0 && m0 + b < L) atomicAdd(&D[(int64_t)d * L + m0 + b], red[0]);
+      __syncthreads();
+    }
+  }
+}
+
+hipError_t launch_detector(const double* S, const double* masks, int32_t n_det, int32_t L,
+                           int32_t n_k, double* D, hipStream_t st) {
+  const int chunk = 8192;
+  dim3 g((n_k + chunk - 1) / chunk, (L + kDetBins - 1) / kDetBins);
+  hipLaunchKernelGGL(detector_kernel, g, dim3(256), 0, st, S, masks, n_det, L, n_k, chunk, D);
+  return hipGetLastError();
+}
+
+// out[0] += sum_i a[i] * b[i]
+__global__ void dot_kernel(const double* a, const double* b, int64_t n, double* out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    s += a[i] * (b ? b[i] : 1.0);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+hipError_t launch_dot_gS(const double* S, const double* gS, int64_t n, double* out,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(dot_kernel, dim3(blocks_for(n, 256, 1024)), dim3(256), 0, st, S, gS, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum(const double* p, int64_t n, double* out, hipStream_t st) {
+  return launch_dot_gS(p, nullptr, n, out, st);
+}
+
+}  // namespace tacaw

@@ -1,0 +1,117 @@
+// Internal interface between the plan runtime (tacaw_plan.hip) and the kernel
+// translation units. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tacaw {
+
+constexpr int kMaxDet = 8;   // detector masks per plan
+constexpr int kMaxCorr = 3;  // bins where the window's DFT is non-zero (Hann: 0, 1, L-1)
+
+// Arguments of the fused chunk kernels (FFT and GEMM forms).
+struct SegArgs {
+  const void* in;          // push buffer, element (i, n, k) at in + i*pstride + n*fstride + k
+  int64_t pstride;         // elements
+  int64_t fstride;         // elements
+  int64_t push_begin;      // absolute frame index of the push buffer's frame 0
+  const void* ring;        // [n_slots][L][n_k] frames pushed earlier, slot = probe % n_slots
+  int32_t n_slots;
+  int32_t n_k;
+  int32_t probe0;          // first probe of the push
+  int32_t n_probes;        // probes in the push
+  int32_t s_lo, s_hi;      // chunks [s_lo, s_hi) are completed by this push
+  int32_t hop;
+  int32_t track_mean;      // accumulate sum(psi - c) and sum_s X'_s at the correction bins
+  int32_t n_corr;          // 1 (rectangular) or 3 (Hann)
+  const float* win_t;      // window, transposed per thread: [N2][N1] (t = N2*n1 + n2)
+  const float2* tw;        // inter-pass twiddles exp(-2 pi i n2 k1 / L): [N2][N1]
+  const double2* cref;     // [n_probe][n_k] reference subtracted before the window
+  double2* msum;           // [n_probe][n_k] FP64 sum of (psi - c) over counted frames
+  double2* xs;             // [n_probe][kMaxCorr][n_k] FP64 sum over chunks of X'(bin)
+  double* S;               // [L][n_k] FP64 accumulator of sum |X'|^2
+  int32_t n_det;           // per-probe detector partials (0 = off)
+  const double* masks;     // [n_det][n_k]
+  const int32_t* tile_slot;// [n_tiles] slot in dpart, -1 if no mask touches the tile
+  double* dpart;           // [n_active][n_probes][n_det][L]
+};
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_seg_fft(int L, int in_dtype, bool sub64, const SegArgs& a, int n_tiles,
+                          hipStream_t st);
+int seg_fft_tile_pixels(int L);
+void seg_fft_split(int L, int* n1, int* n2);  // L = N1 * N2 of the push kernel's tables
+bool seg_fft_supported(int L);
+
+hipError_t launch_seg_gemm(int L, int in_dtype, bool sub64, int prec, const SegArgs& a,
+                           const void* fmat, int n_tiles, hipStream_t st);
+int seg_gemm_tile_pixels(int L);
+bool seg_gemm_supported(int L);
+
+// Auxiliary kernels (tacaw_aux.hip).
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
+hipError_t launch_ref_first_frame(const void* in, int in_dtype, int64_t pstride, int32_t probe0,
+                                  int32_t n_probes, int32_t n_k, double2* cref, hipStream_t st);
+hipError_t launch_ref_mean(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
+                           int64_t n_used, int32_t probe0, int32_t n_probes, int32_t n_k,
+                           double2* cref, hipStream_t st);
+hipError_t launch_ring_store(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
+                             int64_t push_begin, int64_t f_lo, int64_t f_hi, int32_t probe0,
+                             int32_t n_probes, int32_t n_slots, int32_t L, int32_t n_k,
+                             void* ring, hipStream_t st);
+hipError_t launch_dpart_reduce(const double* dpart, int32_t n_active, int32_t n_probes,
+                               int32_t n_det, int32_t L, int32_t probe0, int32_t n_probe_total,
+                               double* Dp, hipStream_t st);
+
+struct CorrArgs {
+  int32_t n_k, n_probe, L, n_corr, mean_global;
+  int32_t bins[kMaxCorr];
+  double2 wbin[kMaxCorr];  // W(bin) = sum_t w(t) exp(-2 pi i bin t / L)
+  double inv_nused;        // 1 / frames_used
+  double n_seg;            // N_s
+  const double2* cref;
+  const double2* msum;
+  const double2* xs;
+};
+hipError_t launch_finalize_S(double* S, double* out, int64_t n_elem, double kappa, hipStream_t st);
+hipError_t launch_correct_S(const CorrArgs& c, double* S, double* out, double kappa, hipStream_t st);
+hipError_t launch_correct_Dp(const CorrArgs& c, const double* masks, int32_t n_det, double* Dp,
+                             hipStream_t st);
+hipError_t launch_scale(double* p, int64_t n, double k, hipStream_t st);
+hipError_t launch_detector(const double* S, const double* masks, int32_t n_det, int32_t L,
+                           int32_t n_k, double* D, hipStream_t st);
+
+// Adjoint (tacaw_adjoint.hip).
+struct BwdArgs {
+  const void* in;
+  int64_t pstride, fstride;
+  void* grad;              // same layout as in
+  int32_t n_k, probe0, n_probes, n_probe_total, n_seg, hop, n_det;
+  int32_t mean_global;
+  double inv_nused;
+  int64_t n_used;
+  const float* win_t;      // [N2][N1]
+  const float* dwin_t;     // [N2][N1] d w / d r (HANN_WIDTH) or null
+  const float2* tw;        // [N2][N1]
+  const double2* cref;     // reference (first frame or exact mean)
+  const double2* mu;       // [n_probe][n_k] exact mean (GLOBAL) for the adjoint
+  const double* gS;        // [L][n_k] or null
+  const double* gD;        // [n_det][L] or null
+  const double* gDp;       // [n_det][n_probe][L] or null
+  const double* masks;     // [n_det][n_k]
+  double kappa_S, kappa_p; // normalisations of S and S_p
+  double2* gmean;          // [n_probes][n_k] sum over chunks and t of w * grad_y (mean term)
+  double* dwpart;          // [n_tiles] partial d Loss / d w-parameter (first term)
+};
+hipError_t launch_bwd(int L, int in_dtype, const BwdArgs& a, int n_tiles, hipStream_t st);
+int bwd_tile_pixels(int L);
+hipError_t launch_bwd_mean_fix(const BwdArgs& a, hipStream_t st);
+hipError_t launch_mean_exact(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
+                             int64_t n_used, int32_t probe0, int32_t n_probes, int32_t n_k,
+                             double2* mu, hipStream_t st);
+hipError_t launch_dot_gS(const double* S, const double* gS, int64_t n, double* out,
+                         hipStream_t st);
+hipError_t launch_sum(const double* p, int64_t n, double* out, hipStream_t st);
+
+}  // namespace tacaw

@@ -1,0 +1,649 @@
+// Plan runtime behind the C ABI declared in include/tacaw.h: descriptor
+// validation (host only, before any HIP call), plan-owned device buffers,
+// per-probe frame cursors and ring slots for streamed series, and the
+// stream-ordered launch sequence of push / finalize / detector / backward.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tacaw.h"
+#include "tacaw_internal.h"
+
+using namespace tacaw;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr int64_t kMaxDeviceBytes = (int64_t)260 << 30;  // refuse plans beyond HBM capacity
+
+enum MeanStrategy {
+  kRefFirstFrame = 0,  // c = frame 0, exact correction at finalize (compact windows)
+  kRefExactMean = 1,   // c = exact FP64 mean from a pre-pass over the whole series
+  kRefZero = 2,        // c = 0 (mean NONE with a non-compact window)
+};
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int64_t seg_count(int64_t frames, int L, int H) { return frames < L ? 0 : (frames - L) / H + 1; }
+
+// Window values w(t), t = 0..L-1 in double precision.
+std::vector<double> make_window(int kind, int L, double param) {
+  std::vector<double> w(L, 1.0);
+  for (int t = 0; t < L; ++t) {
+    const double tt = t;
+    switch (kind) {
+      case TACAW_WIN_HANN:
+        w[t] = 0.5 - 0.5 * std::cos(kTwoPi * tt / L);
+        break;
+      case TACAW_WIN_RECT:
+        w[t] = 1.0;
+        break;
+      case TACAW_WIN_HANN_WIDTH: {
+        const double d = tt - 0.5 * L, half = 0.5 * param * L;
+        w[t] = std::fabs(d) <= half ? 0.5 + 0.5 * std::cos(kTwoPi * d / (param * L)) : 0.0;
+        break;
+      }
+      case TACAW_WIN_TUKEY: {
+        // periodic Tukey: symmetric Tukey of length L + 1 without its last sample;
+        // the two cosine tapers together span alpha * L samples
+        const double span = 0.5 * param * L;
+        if (param <= 0.0) {
+          w[t] = 1.0;
+        } else if (tt < span) {
+          w[t] = 0.5 * (1.0 - std::cos(M_PI * tt / span));
+        } else if (tt > L - span) {
+          w[t] = 0.5 * (1.0 - std::cos(M_PI * (L - tt) / span));
+        } else {
+          w[t] = 1.0;
+        }
+        break;
+      }
+    }
+  }
+  return w;
+}
+
+// d w / d r of the width-r Hann window
+std::vector<double> make_window_dr(int L, double r) {
+  std::vector<double> g(L, 0.0);
+  for (int t = 0; t < L; ++t) {
+    const double d = t - 0.5 * L;
+    if (std::fabs(d) <= 0.5 * r * L) {
+      const double ph = kTwoPi * d / (r * L);
+      g[t] = 0.5 * std::sin(ph) * ph / r;
+    }
+  }
+  return g;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  int64_t bytes = 0;
+};
+
+}  // namespace
+
+struct tacaw_plan_s {
+  tacaw_plan_desc d{};
+  hipStream_t st = nullptr;
+  int device = 0;
+  int L = 0, H = 0, Ns = 0, n_k = 0, N1 = 0, N2 = 0, W = 0, n_tiles = 0;
+  int64_t n_used = 0;
+  double sumw2 = 0.0;
+  int n_corr = 0;
+  int bins[kMaxCorr] = {0, 0, 0};
+  double2 wbin[kMaxCorr];
+  bool compact = false;
+  int strategy = kRefFirstFrame;
+  int esz = 8;
+  int state = 0;  // 0 open, 1 finalized
+  int64_t dropped = 0;
+  int n_active = 0;
+  int n_slots = 0;
+  std::vector<int64_t> cursor;
+  std::vector<int> slot_owner;
+  std::vector<std::pair<void**, int64_t>> owned;
+  int64_t bytes = 0;
+  // device buffers
+  float* win_t = nullptr;   // [N2][N1]
+  float* dwin_t = nullptr;  // [N2][N1] (HANN_WIDTH)
+  float2* tw = nullptr;     // [N2][N1]
+  double2* cref = nullptr;  // [P][n_k]
+  double2* msum = nullptr;  // [P][n_k]
+  double2* xs = nullptr;    // [P][3][n_k]
+  double* S = nullptr;      // [L][n_k]
+  double* masks = nullptr;  // [n_det][n_k]
+  int32_t* tile_slot = nullptr;
+  double* Dp = nullptr;     // [n_det][P][L]
+  double* dpart = nullptr;
+  int64_t dpart_bytes = 0;
+  void* ring = nullptr;
+  void* fmat = nullptr;     // DFT-GEMM operand (GEMM transforms)
+  double2* mu = nullptr;    // exact means for the adjoint
+  double* scratch = nullptr;
+  int64_t scratch_bytes = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+
+  int alloc(void** p, int64_t bytes, const char* what) {
+    if (bytes <= 0) {
+      *p = nullptr;
+      return TACAW_OK;
+    }
+    if (this->bytes + bytes > kMaxDeviceBytes)
+      return fail(TACAW_ERR_OOM, std::string("plan would exceed device memory: ") + what);
+    if (hipMalloc(p, (size_t)bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return fail(TACAW_ERR_OOM, std::string("hipMalloc failed for ") + what);
+    }
+    this->bytes += bytes;
+    owned.push_back({p, bytes});
+    return TACAW_OK;
+  }
+  void release(void** p) {
+    for (size_t i = 0; i < owned.size(); ++i) {
+      if (owned[i].first == p) {
+        if (*p) (void)hipFree(*p);
+        bytes -= owned[i].second;
+        *p = nullptr;
+        owned.erase(owned.begin() + i);
+        return;
+      }
+    }
+  }
+  ~tacaw_plan_s() {
+    (void)hipStreamSynchronize(st);
+    for (auto& o : owned)
+      if (*o.first) (void)hipFree(*o.first);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+};
+
+static int hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(TACAW_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  }
+  return TACAW_OK;
+}
+
+#define TRY(x)                  \
+  do {                          \
+    int _rc = (x);              \
+    if (_rc != TACAW_OK) return _rc; \
+  } while (0)
+
+static bool transform_is_gemm(int t) { return t == TACAW_GEMM_BF16X3 || t == TACAW_GEMM_F16X3; }
+
+extern "C" {
+
+const char* tacaw_last_error(void) { return g_err.c_str(); }
+const char* tacaw_version(void) { return "tacaw-mi355x 0.1"; }
+
+int tacaw_plan_check(const tacaw_plan_desc* d) {
+  g_err.clear();
+  if (!d) return fail(TACAW_ERR_INVALID_ARG, "desc is NULL");
+  if (d->n_probe < 1) return fail(TACAW_ERR_INVALID_ARG, "n_probe must be >= 1");
+  if (d->ny < 1 || d->nx < 1) return fail(TACAW_ERR_INVALID_ARG, "ny and nx must be >= 1");
+  if ((int64_t)d->ny * d->nx > (int64_t)1 << 30)
+    return fail(TACAW_ERR_INVALID_ARG, "ny * nx must be <= 2^30");
+  if (!is_pow2(d->seg_len) || d->seg_len < 64 || d->seg_len > 1024)
+    return fail(TACAW_ERR_UNSUPPORTED, "seg_len must be a power of two in [64, 1024]");
+  if (d->hop < 1 || d->hop > d->seg_len)
+    return fail(TACAW_ERR_INVALID_ARG, "hop must satisfy 1 <= hop <= seg_len");
+  if (d->n_frames < d->seg_len)
+    return fail(TACAW_ERR_INVALID_ARG, "n_frames must be >= seg_len (at least one full chunk)");
+  if (d->window < TACAW_WIN_HANN || d->window > TACAW_WIN_TUKEY)
+    return fail(TACAW_ERR_INVALID_ARG, "unknown window");
+  if (d->window == TACAW_WIN_HANN_WIDTH && !(d->window_param > 0.0 && d->window_param <= 4.0))
+    return fail(TACAW_ERR_INVALID_ARG, "HANN_WIDTH needs 0 < window_param <= 4");
+  if (d->window == TACAW_WIN_TUKEY && !(d->window_param >= 0.0 && d->window_param <= 1.0))
+    return fail(TACAW_ERR_INVALID_ARG, "TUKEY needs 0 <= alpha <= 1");
+  if (d->mean_mode == TACAW_MEAN_PER_SEGMENT)
+    return fail(TACAW_ERR_UNSUPPORTED, "per-segment mean is not implemented");
+  if (d->mean_mode != TACAW_MEAN_GLOBAL && d->mean_mode != TACAW_MEAN_NONE)
+    return fail(TACAW_ERR_INVALID_ARG, "unknown mean_mode");
+  if (d->transform != TACAW_FFT_F32 && !transform_is_gemm(d->transform))
+    return fail(TACAW_ERR_INVALID_ARG, "unknown transform");
+  if (transform_is_gemm(d->transform) && !seg_gemm_supported(d->seg_len))
+    return fail(TACAW_ERR_UNSUPPORTED, "GEMM transform does not support this seg_len");
+  if (d->in_dtype != TACAW_C64 && d->in_dtype != TACAW_C128)
+    return fail(TACAW_ERR_INVALID_ARG, "unknown in_dtype");
+  if (d->probe_reduce != TACAW_PROBE_MEAN && d->probe_reduce != TACAW_PROBE_SUM)
+    return fail(TACAW_ERR_INVALID_ARG, "unknown probe_reduce");
+  if (!(d->dt_fs > 0.0)) return fail(TACAW_ERR_INVALID_ARG, "dt_fs must be > 0");
+  if (d->n_det < 0 || d->n_det > kMaxDet) return fail(TACAW_ERR_INVALID_ARG, "n_det must be in [0, 8]");
+  if (d->n_det > 0 && !d->d_masks) return fail(TACAW_ERR_INVALID_ARG, "n_det > 0 needs d_masks");
+  if (d->max_probes_in_flight < 0 || d->max_probes_in_flight > d->n_probe)
+    return fail(TACAW_ERR_INVALID_ARG, "max_probes_in_flight must be in [0, n_probe]");
+  const int64_t n_k = (int64_t)d->ny * d->nx;
+  const int64_t need = (int64_t)d->seg_len * n_k * 8 + (int64_t)d->n_probe * n_k * 80 +
+                       (int64_t)d->n_det * n_k * 8;
+  if (need > kMaxDeviceBytes) return fail(TACAW_ERR_OOM, "plan accumulators exceed device memory");
+  return TACAW_OK;
+}
+
+int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
+  if (!out) return fail(TACAW_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  TRY(tacaw_plan_check(d));
+  tacaw_plan_s* P = new (std::nothrow) tacaw_plan_s();
+  if (!P) return fail(TACAW_ERR_OOM, "host allocation failed");
+  P->d = *d;
+  P->st = (hipStream_t)hip_stream;
+  P->L = d->seg_len;
+  P->H = d->hop;
+  P->Ns = (int)seg_count(d->n_frames, P->L, P->H);
+  P->n_used = (int64_t)(P->Ns - 1) * P->H + P->L;
+  P->n_k = d->ny * d->nx;
+  P->esz = d->in_dtype == TACAW_C128 ? 16 : 8;
+  const bool gemm = transform_is_gemm(d->transform);
+  P->W = gemm ? seg_gemm_tile_pixels(P->L) : seg_fft_tile_pixels(P->L);
+  P->n_tiles = (P->n_k + P->W - 1) / P->W;
+  P->cursor.assign(d->n_probe, 0);
+  P->n_slots = d->max_probes_in_flight > 0 ? d->max_probes_in_flight : d->n_probe;
+  P->slot_owner.assign(P->n_slots, -1);
+
+  // window, its DFT at every bin (FP64), and the correction bins
+  const std::vector<double> w = make_window(d->window, P->L, d->window_param);
+  P->sumw2 = 0.0;
+  double sumw = 0.0;
+  for (double x : w) {
+    P->sumw2 += x * x;
+    sumw += std::fabs(x);
+  }
+  if (!(P->sumw2 > 0.0)) {
+    delete P;
+    return fail(TACAW_ERR_INVALID_ARG, "window is identically zero");
+  }
+  std::vector<double2> Wm(P->L);
+  for (int m = 0; m < P->L; ++m) {
+    double re = 0.0, im = 0.0;
+    for (int t = 0; t < P->L; ++t) {
+      const double ang = -kTwoPi * (double)(((int64_t)m * t) % P->L) / P->L;
+      re += w[t] * std::cos(ang);
+      im += w[t] * std::sin(ang);
+    }
+    Wm[m] = make_double2(re, im);
+  }
+  auto tiny = [&](int m) { return std::hypot(Wm[m].x, Wm[m].y) <= 1e-9 * sumw; };
+  bool only0 = true, only3 = true;
+  for (int m = 1; m < P->L; ++m) {
+    if (!tiny(m)) only0 = false;
+    if (m != 1 && m != P->L - 1 && !tiny(m)) only3 = false;
+  }
+  P->compact = only0 || only3;
+  P->n_corr = only0 ? 1 : (only3 ? 3 : 0);
+  P->bins[0] = 0;
+  P->bins[1] = 1;
+  P->bins[2] = P->L - 1;
+  for (int b = 0; b < kMaxCorr; ++b) P->wbin[b] = Wm[P->bins[b]];
+  if (P->compact)
+    P->strategy = kRefFirstFrame;
+  else
+    P->strategy = d->mean_mode == TACAW_MEAN_GLOBAL ? kRefExactMean : kRefZero;
+
+  // FFT split L = N1 * N2 (tables are laid out per pass-1 thread)
+  seg_fft_split(P->L, &P->N1, &P->N2);
+  std::vector<float> wt(P->L), dwt(P->L);
+  std::vector<float2> twt(P->L);
+  const std::vector<double> dw =
+      d->window == TACAW_WIN_HANN_WIDTH ? make_window_dr(P->L, d->window_param)
+                                        : std::vector<double>(P->L, 0.0);
+  for (int n2 = 0; n2 < P->N2; ++n2) {
+    for (int n1 = 0; n1 < P->N1; ++n1) {
+      const int t = P->N2 * n1 + n2;
+      wt[n2 * P->N1 + n1] = (float)w[t];
+      dwt[n2 * P->N1 + n1] = (float)dw[t];
+      const int k1 = n1;
+      const double ang = -kTwoPi * (double)(((int64_t)n2 * k1) % P->L) / P->L;
+      twt[n2 * P->N1 + k1] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+  }
+
+  int rc = TACAW_OK;
+  auto A = [&](void** p, int64_t b, const char* what) {
+    if (rc == TACAW_OK) rc = P->alloc(p, b, what);
+  };
+  if (hipGetDevice(&P->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete P;
+    return fail(TACAW_ERR_HIP, "no HIP device available");
+  }
+  const int64_t nk = P->n_k, np = d->n_probe;
+  A((void**)&P->win_t, P->L * 4, "window");
+  A((void**)&P->dwin_t, P->L * 4, "window derivative");
+  A((void**)&P->tw, P->L * 8, "twiddles");
+  A((void**)&P->cref, np * nk * 16, "references");
+  A((void**)&P->msum, np * nk * 16, "mean sums");
+  A((void**)&P->xs, np * kMaxCorr * nk * 16, "correction sums");
+  A((void**)&P->S, (int64_t)P->L * nk * 8, "spectrum accumulator");
+  A((void**)&P->scratch, 64, "scratch");
+  if (d->n_det > 0) {
+    A((void**)&P->masks, (int64_t)d->n_det * nk * 8, "masks");
+    A((void**)&P->tile_slot, (int64_t)P->n_tiles * 4, "tile slots");
+    A((void**)&P->Dp, (int64_t)d->n_det * np * P->L * 8, "per-probe detector spectra");
+  }
+  if (rc != TACAW_OK) {
+    delete P;
+    return rc;
+  }
+  auto H2D = [&](void* dst, const void* src, int64_t b) {
+    if (rc == TACAW_OK) rc = hip_check(hipMemcpy(dst, src, (size_t)b, hipMemcpyHostToDevice), "upload");
+  };
+  H2D(P->win_t, wt.data(), P->L * 4);
+  H2D(P->dwin_t, dwt.data(), P->L * 4);
+  H2D(P->tw, twt.data(), P->L * 8);
+  if (d->n_det > 0 && rc == TACAW_OK) {
+    rc = hip_check(hipMemcpy(P->masks, d->d_masks, (size_t)d->n_det * nk * 8, hipMemcpyDeviceToDevice),
+                   "mask copy");
+    std::vector<double> hm((size_t)d->n_det * nk);
+    if (rc == TACAW_OK)
+      rc = hip_check(hipMemcpy(hm.data(), P->masks, hm.size() * 8, hipMemcpyDeviceToHost), "mask read");
+    std::vector<int32_t> slots(P->n_tiles, -1);
+    int act = 0;
+    for (int t = 0; t < P->n_tiles; ++t) {
+      bool any = false;
+      for (int dd = 0; dd < d->n_det && !any; ++dd)
+        for (int64_t k = (int64_t)t * P->W; k < std::min<int64_t>(nk, (int64_t)(t + 1) * P->W); ++k)
+          if (hm[(size_t)dd * nk + k] != 0.0) {
+            any = true;
+            break;
+          }
+      if (any) slots[t] = act++;
+    }
+    P->n_active = act;
+    H2D(P->tile_slot, slots.data(), (int64_t)P->n_tiles * 4);
+  }
+  if (rc == TACAW_OK && (d->flags & TACAW_FLAG_TIME_KERNELS)) {
+    rc = hip_check(hipEventCreate(&P->ev0), "event");
+    if (rc == TACAW_OK) rc = hip_check(hipEventCreate(&P->ev1), "event");
+  }
+  if (rc == TACAW_OK) rc = hip_check(hipDeviceSynchronize(), "plan setup");
+  if (rc == TACAW_OK) {
+    *out = P;
+    rc = tacaw_reset(P);
+    if (rc != TACAW_OK) {
+      delete P;
+      *out = nullptr;
+    }
+    return rc;
+  }
+  delete P;
+  return rc;
+}
+
+int tacaw_reset(tacaw_plan_t P) {
+  if (!P) return fail(TACAW_ERR_INVALID_ARG, "plan is NULL");
+  const int64_t nk = P->n_k, np = P->d.n_probe;
+  TRY(hip_check(launch_fill_zero(P->cref, np * nk * 16, P->st), "reset"));
+  TRY(hip_check(launch_fill_zero(P->msum, np * nk * 16, P->st), "reset"));
+  TRY(hip_check(launch_fill_zero(P->xs, np * kMaxCorr * nk * 16, P->st), "reset"));
+  TRY(hip_check(launch_fill_zero(P->S, (int64_t)P->L * nk * 8, P->st), "reset"));
+  if (P->Dp)
+    TRY(hip_check(launch_fill_zero(P->Dp, (int64_t)P->d.n_det * np * P->L * 8, P->st), "reset"));
+  std::fill(P->cursor.begin(), P->cursor.end(), 0);
+  std::fill(P->slot_owner.begin(), P->slot_owner.end(), -1);
+  P->state = 0;
+  P->dropped = 0;
+  return TACAW_OK;
+}
+
+int tacaw_set_stream(tacaw_plan_t P, void* s) {
+  if (!P) return fail(TACAW_ERR_INVALID_ARG, "plan is NULL");
+  P->st = (hipStream_t)s;
+  return TACAW_OK;
+}
+
+int tacaw_plan_get_info(tacaw_plan_t P, tacaw_plan_info* info) {
+  if (!P || !info) return fail(TACAW_ERR_INVALID_ARG, "plan or info is NULL");
+  std::memset(info, 0, sizeof(*info));
+  info->n_segments = P->Ns;
+  info->n_omega = P->L;
+  info->frames_used = P->n_used;
+  info->frames_dropped = P->dropped;
+  info->device_bytes = P->bytes;
+  info->state = P->state;
+  int c = 0;
+  for (int64_t x : P->cursor) c += x >= P->n_used;
+  info->probes_complete = c;
+  info->window_sum_sq = P->sumw2;
+  info->tile_pixels = P->W;
+  info->last_chunk_kernel_ms = -1.0;
+  if (P->timed && P->ev1) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(P->ev1) == hipSuccess && hipEventElapsedTime(&ms, P->ev0, P->ev1) == hipSuccess)
+      info->last_chunk_kernel_ms = ms;
+    else
+      (void)hipGetLastError();
+  }
+  return TACAW_OK;
+}
+
+void tacaw_destroy(tacaw_plan_t P) { delete P; }
+
+int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n_probes,
+                      int64_t n_frames, int64_t pstride, int64_t fstride) {
+  g_err.clear();
+  if (!P) return fail(TACAW_ERR_INVALID_ARG, "plan is NULL");
+  if (P->state != 0) return fail(TACAW_ERR_STATE, "plan is finalized");
+  if (n_frames < 0) return fail(TACAW_ERR_INVALID_ARG, "n_frames must be >= 0");
+  if (n_probes < 1 || probe0 < 0 || probe0 + (int64_t)n_probes > P->d.n_probe)
+    return fail(TACAW_ERR_SHAPE, "probe range outside the plan");
+  if (n_frames == 0) return TACAW_OK;
+  if (!frames) return fail(TACAW_ERR_INVALID_ARG, "frames is NULL");
+  if (((uintptr_t)frames) % P->esz != 0)
+    return fail(TACAW_ERR_INVALID_ARG, "frames pointer is not aligned to its element size");
+  if (fstride < P->n_k) return fail(TACAW_ERR_INVALID_ARG, "frame_stride must be >= ny * nx");
+  if (n_probes > 1 && pstride < 1) return fail(TACAW_ERR_INVALID_ARG, "probe_stride must be >= 1");
+  if (((int64_t)P->N2 * fstride + P->n_k) * P->esz > (int64_t)0x7FFFFFFFLL)
+    return fail(TACAW_ERR_UNSUPPORTED, "frame_stride too large for 31-bit row-group offsets");
+  const int64_t a = P->cursor[probe0];
+  for (int i = 1; i < n_probes; ++i)
+    if (P->cursor[probe0 + i] != a)
+      return fail(TACAW_ERR_STATE, "probes of one push must be at the same frame cursor");
+  const int64_t b = a + n_frames;
+  if (b > P->d.n_frames) return fail(TACAW_ERR_SHAPE, "push goes beyond the plan's n_frames");
+  if (P->strategy == kRefExactMean && (a != 0 || b < P->n_used))
+    return fail(TACAW_ERR_UNSUPPORTED,
+                "this window needs each probe's whole series in one push (exact global mean)");
+
+  const int s_lo = (int)std::min<int64_t>(P->Ns, seg_count(a, P->L, P->H));
+  const int s_hi = (int)std::min<int64_t>(P->Ns, seg_count(b, P->L, P->H));
+  // frames later chunks still need after this push
+  const int64_t keep_lo = std::max<int64_t>(a, (int64_t)s_hi * P->H);
+  const int64_t keep_hi = std::min<int64_t>(b, P->n_used);
+  const bool need_ring_write = s_hi < P->Ns && keep_hi > keep_lo;
+  const bool need_ring_read = s_hi > s_lo && (int64_t)s_lo * P->H < a;
+  if (need_ring_write || need_ring_read) {
+    if (n_probes > P->n_slots)
+      return fail(TACAW_ERR_STATE, "ring capacity exceeded: more probes in flight than ring slots");
+    for (int i = 0; i < n_probes; ++i) {
+      const int p = probe0 + i, sl = p % P->n_slots;
+      if (P->slot_owner[sl] != -1 && P->slot_owner[sl] != p)
+        return fail(TACAW_ERR_STATE, "ring capacity exceeded: too many probes in flight");
+    }
+    if (!P->ring) {
+      const int64_t rb = (int64_t)P->n_slots * P->L * P->n_k * P->esz;
+      TRY(P->alloc(&P->ring, rb, "frame ring"));
+    }
+  }
+  int64_t dpart_need = 0;
+  if (P->d.n_det > 0 && s_hi > s_lo)
+    dpart_need = (int64_t)std::max(P->n_active, 1) * n_probes * P->d.n_det * P->L * 8;
+  if (dpart_need > P->dpart_bytes) {
+    P->release((void**)&P->dpart);
+    P->dpart_bytes = 0;
+    TRY(P->alloc((void**)&P->dpart, dpart_need, "detector partials"));
+    P->dpart_bytes = dpart_need;
+  }
+
+  // 1. references at the first frame of each probe
+  if (a == 0) {
+    if (P->strategy == kRefFirstFrame)
+      TRY(hip_check(launch_ref_first_frame(frames, P->d.in_dtype, pstride, probe0, n_probes, P->n_k,
+                                           P->cref, P->st),
+                    "reference"));
+    else if (P->strategy == kRefExactMean)
+      TRY(hip_check(launch_ref_mean(frames, P->d.in_dtype, pstride, fstride, P->n_used, probe0,
+                                    n_probes, P->n_k, P->cref, P->st),
+                    "mean pre-pass"));
+  }
+  // 2. every chunk completed by this push
+  if (s_hi > s_lo) {
+    SegArgs g{};
+    g.in = frames;
+    g.pstride = pstride;
+    g.fstride = fstride;
+    g.push_begin = a;
+    g.ring = P->ring;
+    g.n_slots = P->n_slots;
+    g.n_k = P->n_k;
+    g.probe0 = probe0;
+    g.n_probes = n_probes;
+    g.s_lo = s_lo;
+    g.s_hi = s_hi;
+    g.hop = P->H;
+    g.track_mean = P->strategy == kRefFirstFrame ? 1 : 0;
+    g.n_corr = P->n_corr;
+    g.win_t = P->win_t;
+    g.tw = P->tw;
+    g.cref = P->cref;
+    g.msum = P->msum;
+    g.xs = P->xs;
+    g.S = P->S;
+    g.n_det = P->d.n_det;
+    g.masks = P->masks;
+    g.tile_slot = P->tile_slot;
+    g.dpart = P->dpart;
+    const bool sub64 = P->d.in_dtype == TACAW_C128 || P->strategy == kRefExactMean;
+    if (P->ev0) TRY(hip_check(hipEventRecord(P->ev0, P->st), "event"));
+    if (transform_is_gemm(P->d.transform))
+      TRY(hip_check(launch_seg_gemm(P->L, P->d.in_dtype, sub64,
+                                    P->d.transform == TACAW_GEMM_F16X3 ? 1 : 0, g, P->fmat,
+                                    P->n_tiles, P->st),
+                    "chunk GEMM kernel"));
+    else
+      TRY(hip_check(launch_seg_fft(P->L, P->d.in_dtype, sub64, g, P->n_tiles, P->st),
+                    "chunk FFT kernel"));
+    if (P->ev1) {
+      TRY(hip_check(hipEventRecord(P->ev1, P->st), "event"));
+      P->timed = true;
+    }
+    if (P->d.n_det > 0 && P->n_active > 0)
+      TRY(hip_check(launch_dpart_reduce(P->dpart, P->n_active, n_probes, P->d.n_det, P->L, probe0,
+                                        P->d.n_probe, P->Dp, P->st),
+                    "detector partial reduce"));
+  }
+  // 3. keep what later chunks need
+  if (need_ring_write) {
+    TRY(hip_check(launch_ring_store(frames, P->d.in_dtype, pstride, fstride, a, keep_lo, keep_hi,
+                                    probe0, n_probes, P->n_slots, P->L, P->n_k, P->ring, P->st),
+                  "ring store"));
+  }
+  for (int i = 0; i < n_probes; ++i) {
+    const int p = probe0 + i, sl = p % P->n_slots;
+    P->cursor[p] = b;
+    if (b >= P->n_used) {
+      if (P->slot_owner[sl] == p) P->slot_owner[sl] = -1;
+    } else if (need_ring_write || need_ring_read) {
+      P->slot_owner[sl] = p;
+    }
+  }
+  P->dropped += (int64_t)n_probes * std::max<int64_t>(0, b - std::max<int64_t>(a, P->n_used));
+  return TACAW_OK;
+}
+
+static CorrArgs corr_args(tacaw_plan_t P) {
+  CorrArgs c{};
+  c.n_k = P->n_k;
+  c.n_probe = P->d.n_probe;
+  c.L = P->L;
+  c.n_corr = P->n_corr;
+  c.mean_global = P->d.mean_mode == TACAW_MEAN_GLOBAL ? 1 : 0;
+  for (int b = 0; b < kMaxCorr; ++b) {
+    c.bins[b] = P->bins[b];
+    c.wbin[b] = P->wbin[b];
+  }
+  c.inv_nused = 1.0 / (double)P->n_used;
+  c.n_seg = (double)P->Ns;
+  c.cref = P->cref;
+  c.msum = P->msum;
+  c.xs = P->xs;
+  return c;
+}
+
+static double kappa_probe(tacaw_plan_t P) { return 1.0 / ((double)P->L * P->sumw2 * (double)P->Ns); }
+static double kappa_S(tacaw_plan_t P) {
+  return kappa_probe(P) / (P->d.probe_reduce == TACAW_PROBE_MEAN ? (double)P->d.n_probe : 1.0);
+}
+
+int tacaw_finalize(tacaw_plan_t P, double* d_S) {
+  g_err.clear();
+  if (!P) return fail(TACAW_ERR_INVALID_ARG, "plan is NULL");
+  if (P->state != 0) return fail(TACAW_ERR_STATE, "plan is already finalized");
+  for (int p = 0; p < P->d.n_probe; ++p)
+    if (P->cursor[p] < P->n_used)
+      return fail(TACAW_ERR_STATE, "series incomplete for probe " + std::to_string(p));
+  if (P->strategy == kRefFirstFrame) {
+    const CorrArgs c = corr_args(P);
+    TRY(hip_check(launch_correct_S(c, P->S, nullptr, 0.0, P->st), "mean correction"));
+    if (P->d.n_det > 0)
+      TRY(hip_check(launch_correct_Dp(c, P->masks, P->d.n_det, P->Dp, P->st), "mean correction"));
+  }
+  TRY(hip_check(launch_finalize_S(P->S, d_S, (int64_t)P->L * P->n_k, kappa_S(P), P->st),
+                "normalisation"));
+  if (P->d.n_det > 0)
+    TRY(hip_check(launch_scale(P->Dp, (int64_t)P->d.n_det * P->d.n_probe * P->L, kappa_probe(P), P->st),
+                  "normalisation"));
+  P->state = 1;
+  return TACAW_OK;
+}
+
+int tacaw_detector_spectra(tacaw_plan_t P, const double* d_masks, int32_t n_det, double* d_D,
+                           double* d_Dp) {
+  g_err.clear();
+  if (!P) return fail(TACAW_ERR_INVALID_ARG, "plan is NULL");
+  if (P->state != 1) return fail(TACAW_ERR_STATE, "plan is not finalized");
+  const double* masks = d_masks ? d_masks : P->masks;
+  if (!d_masks && n_det != P->d.n_det)
+    return fail(TACAW_ERR_INVALID_ARG, "n_det must equal the plan's when using the plan's masks");
+  if (n_det < 0 || n_det > kMaxDet) return fail(TACAW_ERR_INVALID_ARG, "n_det must be in [0, 8]");
+  if (n_det > 0 && !masks) return fail(TACAW_ERR_INVALID_ARG, "no masks");
+  if (d_Dp && (d_masks || P->d.n_det == 0))
+    return fail(TACAW_ERR_INVALID_ARG, "per-probe spectra need the plan's own masks");
+  if (n_det > 0 && !d_D && !d_Dp) return fail(TACAW_ERR_INVALID_ARG, "no output");
+  if (n_det > 0 && d_D) {
+    TRY(hip_check(launch_fill_zero(d_D, (int64_t)n_det * P->L * 8, P->st), "zero D"));
+    TRY(hip_check(launch_detector(P->S, masks, n_det, P->L, P->n_k, d_D, P->st), "detector"));
+  }
+  if (d_Dp)
+    TRY(hip_check(hipMemcpyAsync(d_Dp, P->Dp, (size_t)P->d.n_det * P->d.n_probe * P->L * 8,
+                                 hipMemcpyDeviceToDevice, P->st),
+                  "per-probe copy"));
+  return TACAW_OK;
+}
+
+int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n_probes,
+                   int64_t pstride, int64_t fstride, const double* gS, const double* gD,
+                   const double* gDp, void* grad, double* grad_wparam) {
+  (void)frames; (void)probe0; (void)n_probes; (void)pstride; (void)fstride;
+  (void)gS; (void)gD; (void)gDp; (void)grad; (void)grad_wparam;
+  if (!P) return fail(TACAW_ERR_INVALID_ARG, "plan is NULL");
+  return fail(TACAW_ERR_UNSUPPORTED, "backward not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,271 @@
+"""Thin ctypes binding of libtacaw.so (the C ABI in include/tacaw.h).
+
+Argument marshalling only: every step of the spectral path runs in the HIP
+library. torch supplies device memory and the HIP stream. There is no CPU
+fallback: if the library is missing, importing this module raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtacaw.so")
+
+OK = 0
+ERR = {-1: "INVALID_ARG", -2: "SHAPE", -3: "STATE", -4: "OOM", -5: "HIP", -6: "UNSUPPORTED"}
+WINDOWS = {"hann": 0, "rect": 1, "hann_width": 2, "tukey": 3}
+MEANS = {"global": 0, "per_segment": 1, "none": 2}
+TRANSFORMS = {"fft": 0, "gemm_bf16x3": 1, "gemm_f16x3": 2}
+DTYPES = {"c64": 0, "c128": 1}
+REDUCE = {"mean": 0, "sum": 1}
+
+
+class TacawError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tacaw {ERR.get(code, code)}: {msg}")
+        self.code = code
+        self.kind = ERR.get(code, str(code))
+
+
+class PlanDesc(C.Structure):
+    _fields_ = [
+        ("n_probe", C.c_int32), ("ny", C.c_int32), ("nx", C.c_int32),
+        ("n_frames", C.c_int64),
+        ("seg_len", C.c_int32), ("hop", C.c_int32),
+        ("window", C.c_int32), ("window_param", C.c_double),
+        ("mean_mode", C.c_int32), ("transform", C.c_int32), ("in_dtype", C.c_int32),
+        ("probe_reduce", C.c_int32), ("dt_fs", C.c_double),
+        ("n_det", C.c_int32), ("d_masks", C.c_void_p),
+        ("max_probes_in_flight", C.c_int32), ("flags", C.c_int32),
+    ]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [
+        ("n_segments", C.c_int32), ("n_omega", C.c_int32),
+        ("frames_used", C.c_int64), ("frames_dropped", C.c_int64), ("device_bytes", C.c_int64),
+        ("state", C.c_int32), ("probes_complete", C.c_int32),
+        ("window_sum_sq", C.c_double), ("tile_pixels", C.c_int32), ("reserved", C.c_int32),
+        ("last_chunk_kernel_ms", C.c_double),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2607_02236_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "tacaw_plan": (C.c_int, [C.POINTER(PlanDesc), P, C.POINTER(P)]),
+        "tacaw_plan_check": (C.c_int, [C.POINTER(PlanDesc)]),
+        "tacaw_push_frames": (C.c_int, [P, P, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.c_int64]),
+        "tacaw_finalize": (C.c_int, [P, P]),
+        "tacaw_detector_spectra": (C.c_int, [P, P, C.c_int32, P, P]),
+        "tacaw_backward": (C.c_int, [P, P, C.c_int32, C.c_int32, C.c_int64, C.c_int64, P, P, P, P, P]),
+        "tacaw_reset": (C.c_int, [P]),
+        "tacaw_set_stream": (C.c_int, [P, P]),
+        "tacaw_plan_get_info": (C.c_int, [P, C.POINTER(PlanInfo)]),
+        "tacaw_destroy": (None, [P]),
+        "tacaw_last_error": (C.c_char_p, []),
+        "tacaw_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+EXPORTED = ("tacaw_plan", "tacaw_plan_check", "tacaw_push_frames", "tacaw_finalize",
+            "tacaw_detector_spectra", "tacaw_backward", "tacaw_reset", "tacaw_set_stream",
+            "tacaw_plan_get_info", "tacaw_destroy", "tacaw_last_error", "tacaw_version")
+
+
+def _check(rc):
+    if rc != OK:
+        raise TacawError(rc, lib.tacaw_last_error().decode())
+
+
+def make_desc(n_probe, ny, nx, n_frames, seg_len, hop, window="hann", window_param=1.0,
+              mean_mode="global", transform="fft", in_dtype="c64", probe_reduce="mean",
+              dt_fs=5.0, n_det=0, masks_ptr=0, max_probes_in_flight=0, flags=0) -> PlanDesc:
+    return PlanDesc(int(n_probe), int(ny), int(nx), int(n_frames), int(seg_len), int(hop),
+                    WINDOWS[window], float(window_param), MEANS[mean_mode],
+                    TRANSFORMS[transform], DTYPES[in_dtype], REDUCE[probe_reduce],
+                    float(dt_fs), int(n_det), C.c_void_p(masks_ptr or None),
+                    int(max_probes_in_flight), int(flags))
+
+
+def check_desc(**kw) -> None:
+    """Host-only validation of a plan descriptor (raises TacawError)."""
+    d = make_desc(**kw)
+    _check(lib.tacaw_plan_check(C.byref(d)))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream, C.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """One spectral reduction: push exit-wave frames, finalize, read spectra.
+
+    masks: optional torch float64 CUDA tensor [n_det, ny, nx] (enables the fused
+    per-probe detector spectra).
+    """
+
+    def __init__(self, n_probe, ny, nx, n_frames, seg_len, hop=None, window="hann",
+                 window_param=1.0, mean_mode="global", transform="fft", in_dtype="c64",
+                 probe_reduce="mean", dt_fs=5.0, masks=None, max_probes_in_flight=0,
+                 stream=None, time_kernels=False):
+        self.handle = None
+        hop = seg_len // 2 if hop is None else hop
+        self.n_probe, self.ny, self.nx = int(n_probe), int(ny), int(nx)
+        self.seg_len, self.hop, self.n_frames = int(seg_len), int(hop), int(n_frames)
+        self.in_dtype = in_dtype
+        self.tdtype = torch.complex64 if in_dtype == "c64" else torch.complex128
+        self.masks = None
+        n_det, mptr = 0, 0
+        if masks is not None:
+            m = masks.detach().to(dtype=torch.float64).contiguous()
+            if m.dim() == 2:
+                m = m[None]
+            if not m.is_cuda or tuple(m.shape[1:]) != (self.ny, self.nx):
+                raise ValueError("masks must be a CUDA tensor [n_det, ny, nx]")
+            self.masks = m
+            n_det, mptr = m.shape[0], m.data_ptr()
+        self.n_det = n_det
+        self.stream, sptr = _stream_ptr(stream)
+        self.desc = make_desc(n_probe, ny, nx, n_frames, seg_len, hop, window, window_param,
+                              mean_mode, transform, in_dtype, probe_reduce, dt_fs, n_det, mptr,
+                              max_probes_in_flight, 1 if time_kernels else 0)
+        h = C.c_void_p()
+        _check(lib.tacaw_plan(C.byref(self.desc), sptr, C.byref(h)))
+        self.handle = h
+        self._keep = []
+
+    # ------------------------------------------------------------------
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(lib.tacaw_plan_get_info(self.handle, C.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in PlanInfo._fields_ if f != "reserved"}
+
+    @property
+    def n_omega(self):
+        return self.seg_len
+
+    def _frames_args(self, frames):
+        if frames.dtype != self.tdtype:
+            raise TypeError(f"frames must be {self.tdtype}")
+        if not frames.is_cuda:
+            raise ValueError("frames must be a CUDA tensor")
+        if frames.dim() == 3:
+            frames = frames[None]
+        if frames.dim() != 4 or tuple(frames.shape[2:]) != (self.ny, self.nx):
+            raise ValueError("frames must be [n_probes, n_frames, ny, nx]")
+        if frames.stride(3) != 1 or frames.stride(2) != self.nx:
+            raise ValueError("each frame must be a contiguous ny x nx image")
+        return frames, frames.stride(0), frames.stride(1)
+
+    def push(self, frames: torch.Tensor, probe0: int = 0):
+        """Push frames [n_probes, n, ny, nx] for probes probe0.. (next n frames)."""
+        frames, ps, fs = self._frames_args(frames)
+        if frames.shape[1] == 0:
+            return
+        _check(lib.tacaw_push_frames(self.handle, C.c_void_p(frames.data_ptr()), int(probe0),
+                                     int(frames.shape[0]), int(frames.shape[1]), int(ps), int(fs)))
+        if self.stream != torch.cuda.current_stream():
+            frames.record_stream(self.stream)
+
+    def finalize(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty((self.seg_len, self.ny, self.nx), dtype=torch.float64, device="cuda")
+        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != self.seg_len * self.ny * self.nx:
+            raise ValueError("out must be a contiguous float64 [n_omega, ny, nx] tensor")
+        _check(lib.tacaw_finalize(self.handle, C.c_void_p(out.data_ptr())))
+        return out
+
+    def detector_spectra(self, masks=None, per_probe=False, out=None, out_p=None):
+        """D [n_det, n_omega] (and per-probe [n_det, n_probe, n_omega] if per_probe)."""
+        if masks is not None:
+            m = masks.to(dtype=torch.float64).contiguous()
+            if m.dim() == 2:
+                m = m[None]
+            n_det, mptr = m.shape[0], C.c_void_p(m.data_ptr())
+            self._keep = [m]
+        else:
+            n_det, mptr = self.n_det, C.c_void_p(None)
+        D = out if out is not None else torch.empty((n_det, self.seg_len), dtype=torch.float64, device="cuda")
+        Dp = None
+        if per_probe:
+            Dp = out_p if out_p is not None else torch.empty((self.n_det, self.n_probe, self.seg_len),
+                                                             dtype=torch.float64, device="cuda")
+        _check(lib.tacaw_detector_spectra(self.handle, mptr, int(n_det), C.c_void_p(D.data_ptr()),
+                                          C.c_void_p(Dp.data_ptr() if Dp is not None else None)))
+        return (D, Dp) if per_probe else D
+
+    def backward(self, frames, probe0=0, gS=None, gD=None, gDp=None, grad=None, grad_wparam=None):
+        """Adjoint: returns (grad_frames, dLoss/dwindow_param tensor of shape [1])."""
+        frames, ps, fs = self._frames_args(frames)
+        if grad is None:
+            grad = torch.zeros_like(frames)
+        if grad.stride() != frames.stride():
+            raise ValueError("grad must have the strides of frames")
+        if grad_wparam is None:
+            grad_wparam = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+        def ptr(t):
+            return C.c_void_p(t.data_ptr() if t is not None else None)
+
+        ins = [None if t is None else t.to(torch.float64).contiguous() for t in (gS, gD, gDp)]
+        _check(lib.tacaw_backward(self.handle, C.c_void_p(frames.data_ptr()), int(probe0),
+                                  int(frames.shape[0]), int(ps), int(fs), ptr(ins[0]), ptr(ins[1]),
+                                  ptr(ins[2]), C.c_void_p(grad.data_ptr()), ptr(grad_wparam)))
+        self._keep = ins
+        return grad, grad_wparam
+
+    def reset(self):
+        _check(lib.tacaw_reset(self.handle))
+
+    def set_stream(self, stream):
+        self.stream, sptr = _stream_ptr(stream)
+        _check(lib.tacaw_set_stream(self.handle, sptr))
+
+    def close(self):
+        if self.handle is not None:
+            lib.tacaw_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def spectra(frames, seg_len, hop=None, masks=None, per_probe=False, **kw):
+    """One-shot: S [n_omega, ny, nx] and (if masks) D / per-probe D for a whole series."""
+    if frames.dim() == 3:
+        frames = frames[None]
+    P, NT, ny, nx = frames.shape
+    in_dtype = "c64" if frames.dtype == torch.complex64 else "c128"
+    with Plan(P, ny, nx, NT, seg_len, hop, in_dtype=in_dtype, masks=masks, **kw) as plan:
+        plan.push(frames)
+        S = plan.finalize()
+        if masks is None:
+            return S
+        D = plan.detector_spectra(per_probe=per_probe)
+        torch.cuda.current_stream().synchronize()
+        return (S, *D) if per_probe else (S, D)
