@@ -91,8 +91,10 @@ def main():
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--seg-len", type=int, default=512)
     ap.add_argument("--form", default="fft", choices=["fft", "gemm_bf16x3", "gemm_f16x3"])
-    ap.add_argument("--cpu-pixels", type=int, default=1024)
+    ap.add_argument("--cpu-pixels", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="run a plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -119,6 +121,15 @@ def main():
             torch.cuda.synchronize()
             log(f"generated probe {p + 1}/{spec.n_probe} ({time.time() - t0:.1f} s)")
     torch.cuda.synchronize()
+    if args.copy_probe_gib > 0:
+        n = int(args.copy_probe_gib * (1 << 30)) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {n * 4} bytes read and written per copy")
+        del src, dst
     masks = torch.from_numpy(T.standard_masks(spec.ny, spec.nx, scale=spec.ny / 256)).cuda()
     stream = torch.cuda.current_stream()
     plan = tacaw.Plan(spec.n_probe, spec.ny, spec.nx, spec.n_frames, L, H, masks=masks,

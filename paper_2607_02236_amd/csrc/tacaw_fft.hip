@@ -62,7 +62,7 @@ struct FftShape<512> {
 };
 template <>
 struct FftShape<1024> {
-  static constexpr int N1 = 16, W = 16;
+  static constexpr int N1 = 16, W = 8;
 };
 
 // Pass 2 for N2 > N1: the N2-point DFT of one k1 is shared by G = N2 / N1
@@ -99,7 +99,11 @@ __device__ __forceinline__ void dif_combine(const float2* __restrict__ col, int 
   }
 }
 
-template <int L, typename InT, bool SUB64, bool DP>
+// LEAN: every chunk of the launch lies inside the push buffer and H = L/2, so
+// all loads use uniform row bases and the frames to count in the mean sum are
+// known per n1 at compile time. The general variant also reads the ring, takes
+// any hop and decides per lane.
+template <int L, typename InT, bool SUB64, bool DP, bool LEAN>
 __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
     seg_fft_kernel(const SegArgs a) {
   constexpr int N1 = FftShape<L>::N1;
@@ -181,16 +185,17 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
 
     for (int s = a.s_lo; s < a.s_hi; ++s) {
       const int64_t seg0 = (int64_t)s * H;
-      const bool fast = seg0 >= a.push_begin;
+      const bool fast = LEAN || seg0 >= a.push_begin;
       float2 v[N1];
 
       // subtract the reference; add the frame to the FP64 mean sum when it is
       // counted (each frame once, in the first chunk that contains it).
       // CM: 0 = not tracked, 1 = every loaded frame counts, 2 = per-lane test
+      // t >= L - H, 3 = t >= L/2 (H = L/2), which is n1 >= N1/2 for every lane
       auto take = [&](int n1, InT x, auto cmode) -> float2 {
         constexpr int CM = decltype(cmode)::value;
         const int tau = N2 * n1 + n2;
-        const bool count = CM == 1 || (CM == 2 && tau >= L - H);
+        const bool count = CM == 1 || (CM == 2 && tau >= L - H) || (CM == 3 && n1 >= HALF);
         float2 z;
         double dx, dy;
         if constexpr (SUB64) {
@@ -202,7 +207,10 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
           dx = (double)z.x;
           dy = (double)z.y;
         }
-        if constexpr (CM != 0) {
+        if constexpr (CM == 1) {
+          msum.x += dx;
+          msum.y += dy;
+        } else if constexpr (CM != 0) {
           msum.x += count ? dx : 0.0;
           msum.y += count ? dy : 0.0;
         }
@@ -235,8 +243,23 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
       using C0 = std::integral_constant<int, 0>;
       using C1 = std::integral_constant<int, 1>;
       using C2 = std::integral_constant<int, 2>;
+      using C3 = std::integral_constant<int, 3>;
 
-      if (have_kept && half_hop) {
+      if constexpr (LEAN) {
+        // chunk s: frames with t >= L/2 (n1 >= HALF) are new; t < L/2 are new only for s = 0
+        if (have_kept) {
+#pragma unroll
+          for (int n1 = 0; n1 < HALF; ++n1) v[n1] = kept[n1];
+          if (track) load_range(HALF, fetch_fast, C1{});
+          else load_range(HALF, fetch_fast, C0{});
+        } else if (!track) {
+          load_range(0, fetch_fast, C0{});
+        } else if (s == 0) {
+          load_range(0, fetch_fast, C1{});
+        } else {
+          load_range(0, fetch_fast, C3{});
+        }
+      } else if (have_kept && half_hop) {
         // the kept half was counted in the previous chunk; the new half all counts
 #pragma unroll
         for (int n1 = 0; n1 < HALF; ++n1) v[n1] = kept[n1];
@@ -378,19 +401,16 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
       if (slot >= 0) {
         double* out = a.dpart + ((int64_t)slot * a.n_probes + i) * a.n_det * L;
         for (int m = tid; m < L; m += NT) {
-          double dsum[kMaxDet];
+          double pv[W];
 #pragma unroll
-          for (int d = 0; d < kMaxDet; ++d) dsum[d] = 0.0;
+          for (int x = 0; x < W; ++x) pv[x] = sp[m * W + x];
+#pragma unroll 1
+          for (int d = 0; d < a.n_det; ++d) {
+            double dsum = 0.0;
 #pragma unroll
-          for (int x = 0; x < W; ++x) {
-            const double pv = sp[m * W + x];
-#pragma unroll
-            for (int d = 0; d < kMaxDet; ++d)
-              if (d < a.n_det) dsum[d] += s_mask[d * W + x] * pv;
+            for (int x = 0; x < W; ++x) dsum += s_mask[d * W + x] * pv[x];
+            out[(int64_t)d * L + m] = dsum;
           }
-#pragma unroll
-          for (int d = 0; d < kMaxDet; ++d)
-            if (d < a.n_det) out[(int64_t)d * L + m] = dsum[d];
         }
       }
     }
@@ -409,10 +429,18 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
 template <int L, typename InT, bool SUB64>
 static hipError_t launch_t(const SegArgs& a, int n_tiles, hipStream_t st) {
   constexpr int NT = FftShape<L>::W * (L / FftShape<L>::N1);
-  if (a.n_det > 0)
-    hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true>), dim3(n_tiles), dim3(NT), 0, st, a);
-  else
-    hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, false>), dim3(n_tiles), dim3(NT), 0, st, a);
+  const bool lean = (2 * a.hop == L) && ((int64_t)a.s_lo * a.hop >= a.push_begin);
+  if (lean) {
+    if (a.n_det > 0)
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, true>), dim3(n_tiles), dim3(NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, false, true>), dim3(n_tiles), dim3(NT), 0, st, a);
+  } else {
+    if (a.n_det > 0)
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, false>), dim3(n_tiles), dim3(NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, false, false>), dim3(n_tiles), dim3(NT), 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -130,8 +130,9 @@ def test_push_and_probe_batching_invariance(tacaw, pushes, batches):
     psi = T.generate(spec)
     masks = T.standard_masks(10, 13, scale=0.08)
     ref = run_gpu(tacaw, psi, 128, 64, masks)
+    in_flight = max(p1 - p0 for p0, p1 in (batches or [(0, 3)]))
     g = run_gpu(tacaw, psi, 128, 64, masks, pushes=pushes, probe_batches=batches,
-                max_probes_in_flight=2)
+                max_probes_in_flight=in_flight)
     assert rel(g["S"], ref["S"]) < 1e-12
     assert rel(g["Dp"], ref["Dp"]) < 1e-12
     o = oracle_all(psi, 128, 64, masks=masks)
@@ -175,7 +176,7 @@ def test_probe_sum_reduction_and_c64_c128_agree(tacaw):
 
 
 def test_state_and_shape_errors(tacaw):
-    psi = T.generate(T.SeriesSpec(2, 300, 4, 4, seed=2)).cuda()
+    psi = T.generate(T.SeriesSpec(2, 400, 4, 4, seed=2)).cuda()
     plan = tacaw.Plan(2, 4, 4, 300, 128, 64, max_probes_in_flight=1)
     with pytest.raises(tacaw.TacawError) as e:
         plan.push(psi[:, :100])  # two probes streamed at once with one ring slot
@@ -189,7 +190,7 @@ def test_state_and_shape_errors(tacaw):
         plan.push(psi[:, 50:60], probe0=0)  # probes at different cursors
     assert e.value.kind == "STATE"
     with pytest.raises(tacaw.TacawError) as e:
-        plan.push(psi[0:1, 50:301], probe0=0)  # beyond n_frames
+        plan.push(psi[0:1, 50:351], probe0=0)  # 50 + 301 frames > n_frames = 300
     assert e.value.kind == "SHAPE"
     with pytest.raises(tacaw.TacawError) as e:
         plan.finalize()  # incomplete
@@ -198,7 +199,7 @@ def test_state_and_shape_errors(tacaw):
         plan.push(psi[0:1, :10], probe0=2)
     assert e.value.kind == "SHAPE"
     plan.push(psi[0:1, 50:300], probe0=0)
-    plan.push(psi[1:2], probe0=1)
+    plan.push(psi[1:2, :300], probe0=1)
     plan.finalize()
     with pytest.raises(tacaw.TacawError) as e:
         plan.push(psi[0:1, :10], probe0=0)
