@@ -1,0 +1,287 @@
+// Adjoint of the spectral reduction (vector-Jacobian product), chunk by chunk
+// with recomputation: no chunk spectra are stored.
+//
+// For Lval = sum_{p,s,m,k} G_p(m,k) |X_{p,s}(m,k)|^2, X = DFT_t(w (psi - mu)):
+//   g_y(t)  = 2 sum_m G(m) X(m) exp(+2 pi i m t / L)      (d/dRe + i d/dIm)
+//   g_z(t)  = w(t) g_y(t)
+//   grad psi(n) = sum over the chunks holding n of g_z(n - sH)
+//                 - [n < N_used] (1 / N_used) sum_s sum_t g_z_s(t)   (GLOBAL mean)
+//   dLval/dr = sum Re[conj(g_y) z] dw/dr - 2 Lval sum_t w dw/dr / sum_t w^2
+// with G_p(m,k) = kappa_S (gS(m,k) + sum_j gD_j(m) M_j(k)) + kappa_p sum_j gDp_{j,p}(m) M_j(k).
+// The inverse transform is a forward transform of conj(G X) re-laid out through
+// LDS: g_y = 2 conj(DFT(conj(G X))).
+#include "fft_pass.h"
+#include "tacaw_internal.h"
+
+namespace tacaw {
+
+template <int L>
+struct BwdShape;
+template <>
+struct BwdShape<64> {
+  static constexpr int N1 = 8, W = 16;
+};
+template <>
+struct BwdShape<128> {
+  static constexpr int N1 = 16, W = 16;
+};
+template <>
+struct BwdShape<256> {
+  static constexpr int N1 = 16, W = 16;
+};
+template <>
+struct BwdShape<512> {
+  static constexpr int N1 = 16, W = 16;
+};
+template <>
+struct BwdShape<1024> {
+  static constexpr int N1 = 16, W = 8;
+};
+
+template <int L, typename InT>
+__global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
+    bwd_kernel(const BwdArgs a) {
+  constexpr int N1 = BwdShape<L>::N1;
+  constexpr int W = BwdShape<L>::W;
+  using F = Fft2<L, N1, W>;
+  constexpr int N2 = F::N2;
+  constexpr int NT = W * N2;
+  constexpr int HALF = N1 / 2;
+  static_assert(F::LDS >= L * W, "exchange tile must hold a natural-order [L][W] tile");
+
+  __shared__ float2 xbuf[F::LDS];
+  __shared__ float2 s_tw[L];
+  __shared__ float s_win[L];
+  __shared__ float s_dwin[L];
+  __shared__ double red[2 * NT];
+
+  const int tid = threadIdx.x;
+  const int px = tid % W;
+  const int n2 = tid / W;
+  const int tile = blockIdx.x;
+  const int n_k = a.n_k;
+  const int64_t k = (int64_t)tile * W + px;
+  const bool kvalid = k < n_k;
+  const int64_t kc = kvalid ? k : (int64_t)n_k - 1;
+  for (int i = tid; i < L; i += NT) {
+    s_tw[i] = a.tw[i];
+    s_win[i] = a.win_t[i];
+    s_dwin[i] = a.dwin_t ? a.dwin_t[i] : 0.0f;
+  }
+  __syncthreads();
+
+  // masks of this pixel
+  float mk[kMaxDet];
+#pragma unroll
+  for (int d = 0; d < kMaxDet; ++d) mk[d] = (d < a.n_det) ? (float)a.masks[(int64_t)d * n_k + kc] : 0.0f;
+
+  const int H = a.hop;
+  const bool half_hop = (2 * H == L);
+  double dA = 0.0, dLval = 0.0;
+
+  for (int i = 0; i < a.n_probes; ++i) {
+    const int p = a.probe0 + i;
+    // upstream weight for the thread's bins
+    float Gt[N1];
+#pragma unroll
+    for (int t = 0; t < N1; ++t) {
+      const int m = F::bin(t, n2);
+      double g = 0.0;
+      if (a.gS) g += a.kappa_S * a.gS[(int64_t)m * n_k + kc];
+      for (int d = 0; d < a.n_det; ++d) {
+        double c = 0.0;
+        if (a.gD) c += a.kappa_S * a.gD[(int64_t)d * L + m];
+        if (a.gDp) c += a.kappa_p * a.gDp[((int64_t)d * a.n_probe_total + p) * L + m];
+        g += c * (double)mk[d];
+      }
+      Gt[t] = (float)g;
+    }
+    const double2 mu = a.mu ? a.mu[(int64_t)p * n_k + kc] : make_double2(0.0, 0.0);
+    const InT* inp = (const InT*)a.in + (int64_t)i * a.pstride + kc;
+    InT* gp = (InT*)a.grad + (int64_t)i * a.pstride + kc;
+    float2 carry[HALF];
+#pragma unroll
+    for (int u = 0; u < HALF; ++u) carry[u] = make_float2(0.f, 0.f);
+    double2 gsum = make_double2(0.0, 0.0);
+
+    for (int s = 0; s < a.n_seg; ++s) {
+      const int64_t seg0 = (int64_t)s * H;
+      float2 z[N1], v[N1], X[N1];
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) {
+        const InT x = inp[(seg0 + N2 * n1 + n2) * a.fstride];
+        z[n1] = make_float2((float)((double)x.x - mu.x), (float)((double)x.y - mu.y));
+        const float w = s_win[n2 * N1 + n1];
+        v[n1] = make_float2(w * z[n1].x, w * z[n1].y);
+      }
+      F::run(v, X, xbuf, s_tw, px, n2);
+      // weight by G, accumulate the loss value, write conj(G X) in natural order
+#pragma unroll
+      for (int t = 0; t < N1; ++t) {
+        const float pw = X[t].x * X[t].x + X[t].y * X[t].y;
+        dLval += (double)Gt[t] * (double)pw;
+        xbuf[F::bin(t, n2) * W + px] = make_float2(Gt[t] * X[t].x, -Gt[t] * X[t].y);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) v[n1] = xbuf[(N2 * n1 + n2) * W + px];
+      __syncthreads();
+      F::run(v, X, xbuf, s_tw, px, n2);
+      // g_y = 2 conj(X), back to the time layout t = N2 n1 + n2
+#pragma unroll
+      for (int t = 0; t < N1; ++t) xbuf[F::bin(t, n2) * W + px] = make_float2(2.f * X[t].x, -2.f * X[t].y);
+      __syncthreads();
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) v[n1] = xbuf[(N2 * n1 + n2) * W + px];
+      __syncthreads();
+      // g_z = w g_y; r-derivative term; mean-term sum; overlap carry and stores
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) {
+        const float w = s_win[n2 * N1 + n1];
+        const float dw = s_dwin[n2 * N1 + n1];
+        const float2 gy = v[n1];
+        dA += (double)dw * ((double)gy.x * z[n1].x + (double)gy.y * z[n1].y);
+        v[n1] = make_float2(w * gy.x, w * gy.y);
+        gsum.x += (double)v[n1].x;
+        gsum.y += (double)v[n1].y;
+      }
+      const bool last = (s == a.n_seg - 1);
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) {
+        float2 o = v[n1];
+        bool store = true;
+        if (half_hop) {
+          if (n1 < HALF) {
+            o.x += carry[n1].x;
+            o.y += carry[n1].y;
+          } else {
+            carry[n1 - HALF] = o;
+            store = last;
+          }
+        }
+        if (store && kvalid) {
+          InT outv;
+          outv.x = o.x;
+          outv.y = o.y;
+          gp[(seg0 + N2 * n1 + n2) * a.fstride] = outv;
+        }
+      }
+    }
+    // mean-term sum of this probe and pixel
+    double2* rr = reinterpret_cast<double2*>(xbuf);
+    rr[tid] = gsum;
+    __syncthreads();
+    if (n2 == 0 && kvalid) {
+      double2 t = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int r = 0; r < N2; ++r) {
+        t.x += rr[r * W + px].x;
+        t.y += rr[r * W + px].y;
+      }
+      a.gmean[(int64_t)i * n_k + k] = t;
+    }
+    __syncthreads();
+  }
+  // workgroup partials of the r-derivative and the loss value
+  red[tid] = kvalid ? dA : 0.0;
+  red[NT + tid] = kvalid ? dLval : 0.0;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      red[tid] += red[tid + w];
+      red[NT + tid] += red[NT + tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    a.dwpart[2 * tile] = red[0];
+    a.dwpart[2 * tile + 1] = red[NT];
+  }
+}
+
+// grad[i][n][k] -= gmean[i][k] / N_used for n < N_used
+template <typename InT>
+__global__ void bwd_mean_fix_kernel(const BwdArgs a) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.z;
+  if (k >= a.n_k) return;
+  const double2 g = a.gmean[(int64_t)i * a.n_k + k];
+  const double sx = g.x * a.inv_nused, sy = g.y * a.inv_nused;
+  InT* gp = (InT*)a.grad + (int64_t)i * a.pstride + k;
+  for (int64_t n = blockIdx.y; n < a.n_used; n += gridDim.y) {
+    InT v = gp[n * a.fstride];
+    v.x = (decltype(v.x))((double)v.x - sx);
+    v.y = (decltype(v.y))((double)v.y - sy);
+    gp[n * a.fstride] = v;
+  }
+}
+
+// out[0] += sum_t part[2t] - 2 c sum_t part[2t+1]
+__global__ void bwd_wparam_kernel(const double* part, int n, double c, double* out) {
+  __shared__ double ra[256], rl[256];
+  double sa = 0.0, sl = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    sa += part[2 * i];
+    sl += part[2 * i + 1];
+  }
+  ra[threadIdx.x] = sa;
+  rl[threadIdx.x] = sl;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      ra[threadIdx.x] += ra[threadIdx.x + w];
+      rl[threadIdx.x] += rl[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] += ra[0] - 2.0 * c * rl[0];
+}
+
+template <int L>
+static hipError_t launch_bl(int in_dtype, const BwdArgs& a, int n_tiles, hipStream_t st) {
+  constexpr int NT = BwdShape<L>::W * (L / BwdShape<L>::N1);
+  if (in_dtype == 1)
+    hipLaunchKernelGGL((bwd_kernel<L, double2>), dim3(n_tiles), dim3(NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((bwd_kernel<L, float2>), dim3(n_tiles), dim3(NT), 0, st, a);
+  return hipGetLastError();
+}
+
+int bwd_tile_pixels(int L) {
+  switch (L) {
+    case 64: return BwdShape<64>::W;
+    case 128: return BwdShape<128>::W;
+    case 256: return BwdShape<256>::W;
+    case 512: return BwdShape<512>::W;
+    case 1024: return BwdShape<1024>::W;
+  }
+  return 0;
+}
+
+hipError_t launch_bwd(int L, int in_dtype, const BwdArgs& a, int n_tiles, hipStream_t st) {
+  switch (L) {
+    case 64: return launch_bl<64>(in_dtype, a, n_tiles, st);
+    case 128: return launch_bl<128>(in_dtype, a, n_tiles, st);
+    case 256: return launch_bl<256>(in_dtype, a, n_tiles, st);
+    case 512: return launch_bl<512>(in_dtype, a, n_tiles, st);
+    case 1024: return launch_bl<1024>(in_dtype, a, n_tiles, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_bwd_mean_fix(const BwdArgs& a, int in_dtype, hipStream_t st) {
+  const int gy = (int)(a.n_used < 64 ? a.n_used : 64);
+  dim3 g((a.n_k + 255) / 256, gy, a.n_probes);
+  if (in_dtype == 1)
+    hipLaunchKernelGGL(bwd_mean_fix_kernel<double2>, g, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(bwd_mean_fix_kernel<float2>, g, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd_wparam(const double* part, int n, double c, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(bwd_wparam_kernel, dim3(1), dim3(256), 0, st, part, n, c, out);
+  return hipGetLastError();
+}
+
+}  // namespace tacaw

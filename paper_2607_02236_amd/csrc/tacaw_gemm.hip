@@ -1,13 +1,309 @@
-// DFT-as-GEMM chunk kernel on MFMA (split-precision operands). Placeholder
-// until the kernel lands: reports the transform as unsupported.
+// Chunk transform as a dense GEMM on MFMA with split-precision operands.
+//
+// X(m, k) = sum_t F(m, t) y(t, k),  F(m, t) = w(t) exp(-2 pi i m t / L), written as a
+// real GEMM with M = 2L rows (re/im of each bin interleaved), K = 2L (re/im of
+// each frame interleaved) and N = pixels:
+//   [Xr]   [ Fr  -Fi ] [yr]
+//   [Xi] = [ Fi   Fr ] [yi]
+// Both operands are split into a high and a low half-precision part
+// (bf16 or fp16), and X ~= A_hi B_hi + A_hi B_lo + A_lo B_hi is accumulated in
+// FP32 by v_mfma_f32_32x32x16_{bf16,f16}; |X|^2 is accumulated in FP64.
+// y = s (psi - mu) with the exact FP64 mean mu (a pre-pass) and a power-of-two
+// scale s per (probe, pixel) that keeps the fp16 low parts in the normal range
+// (s = 1 for bf16). The power is divided by s^2 before accumulation.
+//
+// Workgroup: 8 waves, a tile of 32 pixels (the MFMA N dimension) and all 2L
+// rows; wave w owns row blocks {w, w + 8, ...} of 32 rows. Frames are staged
+// through LDS in chunks of KC frames, already converted to the operand order.
 #include "tacaw_internal.h"
 
 namespace tacaw {
 
-bool seg_gemm_supported(int) { return false; }
-int seg_gemm_tile_pixels(int) { return 64; }
-hipError_t launch_seg_gemm(int, int, bool, int, const SegArgs&, const void*, int, hipStream_t) {
-  return hipErrorNotSupported;
+typedef __attribute__((__vector_size__(8 * sizeof(short)))) short h8;  // 8 x 16-bit
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int kGemmPx = 32;      // pixels per workgroup (MFMA N)
+constexpr int kGemmWaves = 8;
+constexpr int kGemmKC = 256;     // frames per LDS chunk
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  unsigned u = __builtin_bit_cast(unsigned, x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) {
+  return __builtin_bit_cast(float, ((unsigned)h) << 16);
+}
+
+// split x into hi + lo of the chosen half type (bit patterns)
+template <int PREC>
+__device__ __forceinline__ void split2(float x, unsigned short& hi, unsigned short& lo) {
+  if constexpr (PREC == 0) {  // bf16
+    hi = bf16_rne(x);
+    lo = bf16_rne(x - bf16_to_f(hi));
+  } else {  // fp16
+    const _Float16 h = (_Float16)x;
+    const _Float16 l = (_Float16)(x - (float)h);
+    hi = __builtin_bit_cast(unsigned short, h);
+    lo = __builtin_bit_cast(unsigned short, l);
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ f32x16 mfma(h8 a, h8 b, f32x16 c) {
+  if constexpr (PREC == 0) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  } else {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                  __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+  }
+}
+
+// fmat layout: [2][2L rows][2L] 16-bit (hi then lo), row 2m + c (c = 0 real, 1 imag),
+// column 2t + c' (c' = 0 multiplies Re y, 1 multiplies Im y).
+// gscale: [n_probe][n_k] float, the power-of-two scale s of y.
+template <int L, typename InT, int PREC, bool DP>
+__global__ void __launch_bounds__(64 * kGemmWaves)
+    seg_gemm_kernel(const SegArgs a, const unsigned short* __restrict__ fmat,
+                    const float* __restrict__ gscale) {
+  constexpr int NT = 64 * kGemmWaves;
+  constexpr int MB = L / 16;            // row blocks of 32 rows (2L rows)
+  constexpr int MBW = MB / kGemmWaves;  // row blocks per wave
+  constexpr int KC = L < kGemmKC ? L : kGemmKC;
+  constexpr int KSTEPS = KC / 8;        // 16 real K (8 frames) per MFMA
+  constexpr int K2 = 2 * L;
+  static_assert(MBW >= 1 && MB % kGemmWaves == 0, "row blocks per wave");
+
+  // B operand staging: [kstep][lane][8] hi, then the same for lo, 16-bit
+  __shared__ __attribute__((aligned(16))) unsigned short bst[2 * KSTEPS * 64 * 8];
+  unsigned short* bhi = bst;
+  unsigned short* blo = bst + KSTEPS * 64 * 8;
+  __shared__ double s_mask[DP ? kMaxDet * kGemmPx : 1];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int tile = blockIdx.x;
+  const int n_k = a.n_k;
+  const int col = lane & 31;      // pixel of this lane in MFMA operands and results
+  const int half = lane >> 5;
+  const int64_t kcol = (int64_t)tile * kGemmPx + col;
+  const bool cvalid = kcol < n_k;
+
+  if constexpr (DP) {
+    for (int i = tid; i < kMaxDet * kGemmPx; i += NT) {
+      const int d = i / kGemmPx, x = i % kGemmPx;
+      const int64_t kk = (int64_t)tile * kGemmPx + x;
+      s_mask[i] = (d < a.n_det && kk < n_k) ? a.masks[(int64_t)d * n_k + kk] : 0.0;
+    }
+  }
+
+  // staging role: thread handles pixel sp = tid % 32 and frame groups of 4
+  const int sp = tid & 31;
+  const int sgrp = tid >> 5;  // 0..15
+  const int64_t ks = (int64_t)tile * kGemmPx + sp;
+  const int64_t ksc = ks < n_k ? ks : (int64_t)n_k - 1;
+
+  double acc64[MBW][8];
+#pragma unroll
+  for (int b = 0; b < MBW; ++b)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc64[b][q] = 0.0;
+
+  for (int i = 0; i < a.n_probes; ++i) {
+    const int p = a.probe0 + i;
+    const double2 mu = a.cref[(int64_t)p * n_k + ksc];
+    const float sc = gscale[(int64_t)p * n_k + ksc];
+    const float sc_col = gscale[(int64_t)p * n_k + (cvalid ? kcol : (int64_t)n_k - 1)];
+    const float inv2 = 1.0f / (sc_col * sc_col);
+    const InT* inb = (const InT*)a.in + (int64_t)i * a.pstride + ksc;
+
+    for (int s = a.s_lo; s < a.s_hi; ++s) {
+      const int64_t seg0 = (int64_t)s * a.hop - a.push_begin;
+      f32x16 acc[MBW];
+#pragma unroll
+      for (int b = 0; b < MBW; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[b][v] = 0.0f;
+
+      for (int c0 = 0; c0 < L; c0 += KC) {
+        __syncthreads();  // previous chunk's operand reads are complete
+        // stage frames [c0, c0 + KC) of this chunk: groups of 4 frames per lane slot
+        for (int g4 = sgrp; g4 < KC / 4; g4 += NT / 32) {
+          const int t0 = c0 + 4 * g4;
+          unsigned short hv[8], lv[8];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const InT x = inb[(seg0 + t0 + u) * a.fstride];
+            const float yr = (float)(((double)x.x - mu.x) * (double)sc);
+            const float yi = (float)(((double)x.y - mu.y) * (double)sc);
+            split2<PREC>(yr, hv[2 * u], lv[2 * u]);
+            split2<PREC>(yi, hv[2 * u + 1], lv[2 * u + 1]);
+          }
+          const int tl = 4 * g4;                    // frame within the chunk
+          const int kst = tl / 8, hh = (tl % 8) / 4;
+          const int slot = (kst * 64 + (sp + 32 * hh)) * 8;
+          uint4 H, Lw;
+          H.x = hv[0] | ((unsigned)hv[1] << 16);
+          H.y = hv[2] | ((unsigned)hv[3] << 16);
+          H.z = hv[4] | ((unsigned)hv[5] << 16);
+          H.w = hv[6] | ((unsigned)hv[7] << 16);
+          Lw.x = lv[0] | ((unsigned)lv[1] << 16);
+          Lw.y = lv[2] | ((unsigned)lv[3] << 16);
+          Lw.z = lv[4] | ((unsigned)lv[5] << 16);
+          Lw.w = lv[6] | ((unsigned)lv[7] << 16);
+          *reinterpret_cast<uint4*>(&bhi[slot]) = H;
+          *reinterpret_cast<uint4*>(&blo[slot]) = Lw;
+        }
+        __syncthreads();
+        for (int kst = 0; kst < KSTEPS; ++kst) {
+          const h8 bh = *reinterpret_cast<const h8*>(&bhi[(kst * 64 + lane) * 8]);
+          const h8 bl = *reinterpret_cast<const h8*>(&blo[(kst * 64 + lane) * 8]);
+          const int kcol2 = 2 * c0 + 16 * kst + 8 * half;  // first of the lane's 8 K columns
+#pragma unroll
+          for (int b = 0; b < MBW; ++b) {
+            const int row = 32 * (wave + kGemmWaves * b) + col;
+            const h8 ah = *reinterpret_cast<const h8*>(fmat + (int64_t)row * K2 + kcol2);
+            const h8 al = *reinterpret_cast<const h8*>(fmat + (int64_t)(K2 + row) * K2 + kcol2);
+            acc[b] = mfma<PREC>(ah, bh, acc[b]);
+            acc[b] = mfma<PREC>(ah, bl, acc[b]);
+            acc[b] = mfma<PREC>(al, bh, acc[b]);
+          }
+        }
+      }
+      // |X|^2: accumulator v of a lane holds row 8 (v / 4) + 4 half + (v % 4) of
+      // its 32-row block, column col; rows (2m', 2m'+1) are (Re, Im) of one bin
+#pragma unroll
+      for (int b = 0; b < MBW; ++b) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int v = 4 * (q / 2) + 2 * (q % 2);
+          const float pw = acc[b][v] * acc[b][v] + acc[b][v + 1] * acc[b][v + 1];
+          acc64[b][q] += (double)(pw * inv2);
+        }
+      }
+    }
+
+    if constexpr (DP) {
+      // cumulative per-probe detector partials through LDS, two halves of the bins
+      double* sd = reinterpret_cast<double*>(bst);  // needs L/2 * 32 doubles
+      static_assert(sizeof(bst) >= (size_t)L / 2 * kGemmPx * 8, "LDS for partials");
+      const int slot = a.tile_slot[tile];
+      for (int hb = 0; hb < 2; ++hb) {
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < MBW; ++b) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int rblk = wave + kGemmWaves * b;
+            const int m = 16 * rblk + 4 * (q / 2) + 2 * half + (q % 2);
+            if ((m >= L / 2) == (hb == 1)) sd[(m - hb * (L / 2)) * kGemmPx + col] = acc64[b][q];
+          }
+        }
+        __syncthreads();
+        if (slot >= 0) {
+          double* out = a.dpart + ((int64_t)slot * a.n_probes + i) * a.n_det * L;
+          for (int mm = tid; mm < L / 2; mm += NT) {
+            for (int d = 0; d < a.n_det; ++d) {
+              double dsum = 0.0;
+#pragma unroll
+              for (int x = 0; x < kGemmPx; ++x) dsum += s_mask[d * kGemmPx + x] * sd[mm * kGemmPx + x];
+              out[(int64_t)d * L + hb * (L / 2) + mm] = dsum;
+            }
+          }
+        }
+      }
+    }
+  }
+
+  if (cvalid) {
+#pragma unroll
+    for (int b = 0; b < MBW; ++b) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int rblk = wave + kGemmWaves * b;
+        const int m = 16 * rblk + 4 * (q / 2) + 2 * half + (q % 2);
+        a.S[(int64_t)m * n_k + kcol] += acc64[b][q];
+      }
+    }
+  }
+}
+
+template <int L, typename InT, int PREC>
+static hipError_t launch_g3(const SegArgs& a, const void* fmat, const float* gscale, int n_tiles,
+                            hipStream_t st) {
+  if (a.n_det > 0)
+    hipLaunchKernelGGL((seg_gemm_kernel<L, InT, PREC, true>), dim3(n_tiles), dim3(64 * kGemmWaves),
+                       0, st, a, (const unsigned short*)fmat, gscale);
+  else
+    hipLaunchKernelGGL((seg_gemm_kernel<L, InT, PREC, false>), dim3(n_tiles), dim3(64 * kGemmWaves),
+                       0, st, a, (const unsigned short*)fmat, gscale);
+  return hipGetLastError();
+}
+
+template <int L>
+static hipError_t launch_g2(int in_dtype, int prec, const SegArgs& a, const void* fmat,
+                            const float* gscale, int n_tiles, hipStream_t st) {
+  if (in_dtype == 1)
+    return prec ? launch_g3<L, double2, 1>(a, fmat, gscale, n_tiles, st)
+                : launch_g3<L, double2, 0>(a, fmat, gscale, n_tiles, st);
+  return prec ? launch_g3<L, float2, 1>(a, fmat, gscale, n_tiles, st)
+              : launch_g3<L, float2, 0>(a, fmat, gscale, n_tiles, st);
+}
+
+bool seg_gemm_supported(int L) { return L == 128 || L == 256 || L == 512; }
+int seg_gemm_tile_pixels(int) { return kGemmPx; }
+
+hipError_t launch_seg_gemm(int L, int in_dtype, bool /*sub64*/, int prec, const SegArgs& a,
+                           const void* fmat, int n_tiles, hipStream_t st) {
+  const float* gscale = a.gscale;
+  switch (L) {
+    case 128: return launch_g2<128>(in_dtype, prec, a, fmat, gscale, n_tiles, st);
+    case 256: return launch_g2<256>(in_dtype, prec, a, fmat, gscale, n_tiles, st);
+    case 512: return launch_g2<512>(in_dtype, prec, a, fmat, gscale, n_tiles, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Per (probe, pixel) power-of-two scale s = 2^-e with 2^e > 2 max_n |psi_n - c|
+// over frames [0, n_used) (c = the subtracted reference), so |s (psi - c)| < 1/2
+// and fp16 low parts stay normal; s = 1 for bf16.
+template <typename InT>
+__global__ void gemm_scale_kernel(const InT* in, int64_t pstride, int64_t fstride, int64_t n_used,
+                                  int32_t probe0, int32_t n_probes, int32_t n_k, int32_t prec,
+                                  const double2* cref, float* scale) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (k >= n_k || i >= n_probes) return;
+  const InT* p = in + (int64_t)i * pstride + k;
+  const double2 c = cref[(int64_t)(probe0 + i) * n_k + k];
+  double mx = 0.0;
+  for (int64_t n = 0; n < n_used; ++n) {
+    const InT v = p[n * fstride];
+    mx = fmax(mx, fmax(fabs((double)v.x - c.x), fabs((double)v.y - c.y)));
+  }
+  float s = 1.0f;
+  if (prec == 1 && mx > 0.0) {
+    int e = 0;
+    frexp(2.0 * mx, &e);  // 2 mx < 2^e
+    e = e < -100 ? -100 : (e > 100 ? 100 : e);
+    s = ldexpf(1.0f, -e);
+  }
+  scale[(int64_t)(probe0 + i) * n_k + k] = s;
+}
+
+hipError_t launch_gemm_scale(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
+                             int64_t n_used, int32_t probe0, int32_t n_probes, int32_t n_k,
+                             int prec, const double2* cref, float* scale, hipStream_t st) {
+  dim3 g((n_k + 255) / 256, n_probes);
+  if (in_dtype == 1)
+    hipLaunchKernelGGL(gemm_scale_kernel<double2>, g, dim3(256), 0, st, (const double2*)in, pstride,
+                       fstride, n_used, probe0, n_probes, n_k, prec, cref, scale);
+  else
+    hipLaunchKernelGGL(gemm_scale_kernel<float2>, g, dim3(256), 0, st, (const float2*)in, pstride,
+                       fstride, n_used, probe0, n_probes, n_k, prec, cref, scale);
+  return hipGetLastError();
 }
 
 }  // namespace tacaw

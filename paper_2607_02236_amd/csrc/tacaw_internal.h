@@ -35,6 +35,7 @@ struct SegArgs {
   const double* masks;     // [n_det][n_k]
   const int32_t* tile_slot;// [n_tiles] slot in dpart, -1 if no mask touches the tile
   double* dpart;           // [n_active][n_probes][n_det][L]
+  const float* gscale;     // GEMM form: [n_probe][n_k] power-of-two scale of psi - mu
 };
 
 // Launchers (return hipError_t of the launch).
@@ -48,6 +49,9 @@ hipError_t launch_seg_gemm(int L, int in_dtype, bool sub64, int prec, const SegA
                            const void* fmat, int n_tiles, hipStream_t st);
 int seg_gemm_tile_pixels(int L);
 bool seg_gemm_supported(int L);
+hipError_t launch_gemm_scale(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
+                             int64_t n_used, int32_t probe0, int32_t n_probes, int32_t n_k,
+                             int prec, const double2* cref, float* scale, hipStream_t st);
 
 // Auxiliary kernels (tacaw_aux.hip).
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
@@ -102,11 +106,12 @@ struct BwdArgs {
   const double* masks;     // [n_det][n_k]
   double kappa_S, kappa_p; // normalisations of S and S_p
   double2* gmean;          // [n_probes][n_k] sum over chunks and t of w * grad_y (mean term)
-  double* dwpart;          // [n_tiles] partial d Loss / d w-parameter (first term)
+  double* dwpart;          // [n_tiles][2] partial sums: r-derivative term, loss value
 };
 hipError_t launch_bwd(int L, int in_dtype, const BwdArgs& a, int n_tiles, hipStream_t st);
 int bwd_tile_pixels(int L);
-hipError_t launch_bwd_mean_fix(const BwdArgs& a, hipStream_t st);
+hipError_t launch_bwd_mean_fix(const BwdArgs& a, int in_dtype, hipStream_t st);
+hipError_t launch_bwd_wparam(const double* part, int n, double c, double* out, hipStream_t st);
 hipError_t launch_mean_exact(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
                              int64_t n_used, int32_t probe0, int32_t n_probes, int32_t n_k,
                              double2* mu, hipStream_t st);

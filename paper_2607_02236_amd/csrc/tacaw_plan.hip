@@ -87,10 +87,62 @@ std::vector<double> make_window_dr(int L, double r) {
   return g;
 }
 
-struct DevBuf {
-  void* p = nullptr;
-  int64_t bytes = 0;
-};
+uint16_t bf16_bits(float x) {  // round to nearest even
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+uint16_t f16_bits(float x) {
+  const _Float16 h = (_Float16)x;
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
+float f16_value(uint16_t b) {
+  _Float16 h;
+  std::memcpy(&h, &b, 2);
+  return (float)h;
+}
+
+// Window-folded DFT matrix of the GEMM form as hi and lo 16-bit parts:
+// [2][2L][2L], row 2m + c (c: 0 real, 1 imaginary part of bin m), column 2t + c'
+// (c' multiplies Re or Im of frame t): [[Fr, -Fi], [Fi, Fr]] interleaved.
+std::vector<uint16_t> make_dft_matrix(const std::vector<double>& w, bool fp16) {
+  const int L = (int)w.size(), K2 = 2 * L;
+  std::vector<uint16_t> out((size_t)2 * K2 * K2);
+  for (int m = 0; m < L; ++m) {
+    for (int t = 0; t < L; ++t) {
+      const double ang = -6.283185307179586476925286766559 * (double)(((int64_t)m * t) % L) / L;
+      const double fr = w[t] * std::cos(ang), fi = w[t] * std::sin(ang);
+      const double e[2][2] = {{fr, -fi}, {fi, fr}};
+      for (int c = 0; c < 2; ++c) {
+        for (int cp = 0; cp < 2; ++cp) {
+          const double v = e[c][cp];
+          const float vf = (float)v;
+          uint16_t hi, lo;
+          if (fp16) {
+            hi = f16_bits(vf);
+            lo = f16_bits((float)(v - (double)f16_value(hi)));
+          } else {
+            hi = bf16_bits(vf);
+            lo = bf16_bits((float)(v - (double)bf16_value(hi)));
+          }
+          const size_t idx = (size_t)(2 * m + c) * K2 + (2 * t + cp);
+          out[idx] = hi;
+          out[(size_t)K2 * K2 + idx] = lo;
+        }
+      }
+    }
+  }
+  return out;
+}
 
 }  // namespace
 
@@ -133,6 +185,7 @@ struct tacaw_plan_s {
   double2* mu = nullptr;    // exact means for the adjoint
   double* scratch = nullptr;
   int64_t scratch_bytes = 0;
+  float* gscale = nullptr;  // GEMM form: [P][n_k]
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
 
@@ -291,7 +344,9 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   P->bins[1] = 1;
   P->bins[2] = P->L - 1;
   for (int b = 0; b < kMaxCorr; ++b) P->wbin[b] = Wm[P->bins[b]];
-  if (P->compact)
+  if (gemm)  // the GEMM form subtracts the exact mean (or zero) before splitting
+    P->strategy = d->mean_mode == TACAW_MEAN_GLOBAL ? kRefExactMean : kRefZero;
+  else if (P->compact)
     P->strategy = kRefFirstFrame;
   else
     P->strategy = d->mean_mode == TACAW_MEAN_GLOBAL ? kRefExactMean : kRefZero;
@@ -332,6 +387,10 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   A((void**)&P->xs, np * kMaxCorr * nk * 16, "correction sums");
   A((void**)&P->S, (int64_t)P->L * nk * 8, "spectrum accumulator");
   A((void**)&P->scratch, 64, "scratch");
+  if (gemm) {
+    A(&P->fmat, (int64_t)2 * (2 * P->L) * (2 * P->L) * 2, "DFT matrix");
+    A((void**)&P->gscale, np * nk * 4, "operand scales");
+  }
   if (d->n_det > 0) {
     A((void**)&P->masks, (int64_t)d->n_det * nk * 8, "masks");
     A((void**)&P->tile_slot, (int64_t)P->n_tiles * 4, "tile slots");
@@ -347,6 +406,10 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   H2D(P->win_t, wt.data(), P->L * 4);
   H2D(P->dwin_t, dwt.data(), P->L * 4);
   H2D(P->tw, twt.data(), P->L * 8);
+  if (gemm && rc == TACAW_OK) {
+    const std::vector<uint16_t> fm = make_dft_matrix(w, d->transform == TACAW_GEMM_F16X3);
+    H2D(P->fmat, fm.data(), (int64_t)fm.size() * 2);
+  }
   if (d->n_det > 0 && rc == TACAW_OK) {
     rc = hip_check(hipMemcpy(P->masks, d->d_masks, (size_t)d->n_det * nk * 8, hipMemcpyDeviceToDevice),
                    "mask copy");
@@ -457,9 +520,10 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
       return fail(TACAW_ERR_STATE, "probes of one push must be at the same frame cursor");
   const int64_t b = a + n_frames;
   if (b > P->d.n_frames) return fail(TACAW_ERR_SHAPE, "push goes beyond the plan's n_frames");
-  if (P->strategy == kRefExactMean && (a != 0 || b < P->n_used))
+  if ((P->strategy == kRefExactMean || transform_is_gemm(P->d.transform)) &&
+      (a != 0 || b < P->n_used))
     return fail(TACAW_ERR_UNSUPPORTED,
-                "this window needs each probe's whole series in one push (exact global mean)");
+                "this plan needs each probe's whole series in one push (exact mean pre-pass)");
 
   const int s_lo = (int)std::min<int64_t>(P->Ns, seg_count(a, P->L, P->H));
   const int s_hi = (int)std::min<int64_t>(P->Ns, seg_count(b, P->L, P->H));
@@ -501,6 +565,11 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
       TRY(hip_check(launch_ref_mean(frames, P->d.in_dtype, pstride, fstride, P->n_used, probe0,
                                     n_probes, P->n_k, P->cref, P->st),
                     "mean pre-pass"));
+    if (transform_is_gemm(P->d.transform))
+      TRY(hip_check(launch_gemm_scale(frames, P->d.in_dtype, pstride, fstride, P->n_used, probe0,
+                                      n_probes, P->n_k, P->d.transform == TACAW_GEMM_F16X3 ? 1 : 0,
+                                      P->cref, P->gscale, P->st),
+                    "operand scale pre-pass"));
   }
   // 2. every chunk completed by this push
   if (s_hi > s_lo) {
@@ -529,6 +598,7 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
     g.masks = P->masks;
     g.tile_slot = P->tile_slot;
     g.dpart = P->dpart;
+    g.gscale = P->gscale;
     const bool sub64 = P->d.in_dtype == TACAW_C128 || P->strategy == kRefExactMean;
     if (P->ev0) TRY(hip_check(hipEventRecord(P->ev0, P->st), "event"));
     if (transform_is_gemm(P->d.transform))
@@ -640,10 +710,78 @@ int tacaw_detector_spectra(tacaw_plan_t P, const double* d_masks, int32_t n_det,
 int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n_probes,
                    int64_t pstride, int64_t fstride, const double* gS, const double* gD,
                    const double* gDp, void* grad, double* grad_wparam) {
-  (void)frames; (void)probe0; (void)n_probes; (void)pstride; (void)fstride;
-  (void)gS; (void)gD; (void)gDp; (void)grad; (void)grad_wparam;
+  g_err.clear();
   if (!P) return fail(TACAW_ERR_INVALID_ARG, "plan is NULL");
-  return fail(TACAW_ERR_UNSUPPORTED, "backward not built yet");
+  if (P->state != 1) return fail(TACAW_ERR_STATE, "plan is not finalized");
+  if (!frames || !grad) return fail(TACAW_ERR_INVALID_ARG, "frames and grad must be given");
+  if (((uintptr_t)frames) % P->esz != 0 || ((uintptr_t)grad) % P->esz != 0)
+    return fail(TACAW_ERR_INVALID_ARG, "frames/grad not aligned to their element size");
+  if (n_probes < 1 || probe0 < 0 || probe0 + (int64_t)n_probes > P->d.n_probe)
+    return fail(TACAW_ERR_SHAPE, "probe range outside the plan");
+  if (fstride < P->n_k) return fail(TACAW_ERR_INVALID_ARG, "frame_stride must be >= ny * nx");
+  if (n_probes > 1 && pstride < 1) return fail(TACAW_ERR_INVALID_ARG, "probe_stride must be >= 1");
+  if (P->H != P->L && 2 * P->H != P->L)
+    return fail(TACAW_ERR_UNSUPPORTED, "backward supports hop = L or hop = L/2");
+  if ((gD || gDp) && P->d.n_det == 0)
+    return fail(TACAW_ERR_INVALID_ARG, "detector gradients need plan masks");
+  int n1b = 0, n2b = 0;
+  seg_fft_split(P->L, &n1b, &n2b);
+  if (n1b != P->N1) return fail(TACAW_ERR_UNSUPPORTED, "table split mismatch");
+  const bool global = P->d.mean_mode == TACAW_MEAN_GLOBAL;
+  const int Wb = bwd_tile_pixels(P->L);
+  const int n_tiles = (P->n_k + Wb - 1) / Wb;
+  if (global && !P->mu)
+    TRY(P->alloc((void**)&P->mu, (int64_t)P->d.n_probe * P->n_k * 16, "adjoint means"));
+  const int64_t need = (int64_t)n_probes * P->n_k * 16 + (int64_t)n_tiles * 16;
+  if (need > P->scratch_bytes) {
+    P->release((void**)&P->scratch);
+    P->scratch_bytes = 0;
+    TRY(P->alloc((void**)&P->scratch, need, "adjoint scratch"));
+    P->scratch_bytes = need;
+  }
+  if (global)
+    TRY(hip_check(launch_mean_exact(frames, P->d.in_dtype, pstride, fstride, P->n_used, probe0,
+                                    n_probes, P->n_k, P->mu, P->st),
+                  "adjoint mean"));
+  BwdArgs b{};
+  b.in = frames;
+  b.pstride = pstride;
+  b.fstride = fstride;
+  b.grad = grad;
+  b.n_k = P->n_k;
+  b.probe0 = probe0;
+  b.n_probes = n_probes;
+  b.n_probe_total = P->d.n_probe;
+  b.n_seg = P->Ns;
+  b.hop = P->H;
+  b.n_det = P->d.n_det;
+  b.mean_global = global ? 1 : 0;
+  b.inv_nused = 1.0 / (double)P->n_used;
+  b.n_used = P->n_used;
+  b.win_t = P->win_t;
+  b.dwin_t = P->d.window == TACAW_WIN_HANN_WIDTH ? P->dwin_t : nullptr;
+  b.tw = P->tw;
+  b.cref = P->cref;
+  b.mu = global ? P->mu : nullptr;
+  b.gS = gS;
+  b.gD = gD;
+  b.gDp = gDp;
+  b.masks = P->masks;
+  b.kappa_S = kappa_S(P);
+  b.kappa_p = kappa_probe(P);
+  b.gmean = (double2*)P->scratch;
+  b.dwpart = P->scratch + (int64_t)n_probes * P->n_k * 2;
+  TRY(hip_check(launch_bwd(P->L, P->d.in_dtype, b, n_tiles, P->st), "adjoint kernel"));
+  if (global) TRY(hip_check(launch_bwd_mean_fix(b, P->d.in_dtype, P->st), "adjoint mean term"));
+  if (grad_wparam && P->d.window == TACAW_WIN_HANN_WIDTH) {
+    const std::vector<double> w = make_window(P->d.window, P->L, P->d.window_param);
+    const std::vector<double> dw = make_window_dr(P->L, P->d.window_param);
+    double swd = 0.0;
+    for (int t = 0; t < P->L; ++t) swd += w[t] * dw[t];
+    TRY(hip_check(launch_bwd_wparam(b.dwpart, n_tiles, swd / P->sumw2, grad_wparam, P->st),
+                  "window-parameter gradient"));
+  }
+  return TACAW_OK;
 }
 
 }  // extern "C"
