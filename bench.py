@@ -91,6 +91,9 @@ def main():
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--seg-len", type=int, default=512)
     ap.add_argument("--form", default="fft", choices=["fft", "gemm_bf16x3", "gemm_f16x3"])
+    ap.add_argument("--workload", default="realistic", choices=["realistic", "precision"],
+                    help="realistic: 64 probes x 2048 frames x 256^2 c64 (default); precision: "
+                         "1 probe x 512 frames x 64^2 c128, one chunk of 512")
     ap.add_argument("--cpu-pixels", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
@@ -109,10 +112,15 @@ def main():
     from paper_2607_02236_amd import tacaw
 
     torch.cuda.set_device(0)
-    L, H = args.seg_len, args.seg_len // 2
-    spec = T.config_realistic(n_probe=args.probes, n_frames=args.frames, ny=args.grid, nx=args.grid)
+    if args.workload == "precision":
+        L, H = 512, 512
+        spec = T.config_precision(n_frames=512)
+    else:
+        L, H = args.seg_len, args.seg_len // 2
+        spec = T.config_realistic(n_probe=args.probes, n_frames=args.frames, ny=args.grid,
+                                  nx=args.grid)
     log(f"allocating {spec.nbytes / 1e9:.1f} GB of exit waves on the GPU")
-    psi = torch.empty((spec.n_probe, spec.n_frames, spec.ny, spec.nx), dtype=torch.complex64,
+    psi = torch.empty((spec.n_probe, spec.n_frames, spec.ny, spec.nx), dtype=spec.torch_dtype,
                       device="cuda")
     t0 = time.time()
     for p in range(spec.n_probe):
@@ -131,9 +139,12 @@ def main():
         log(f"copy probe: {n * 4} bytes read and written per copy")
         del src, dst
     masks = torch.from_numpy(T.standard_masks(spec.ny, spec.nx, scale=spec.ny / 256)).cuda()
+    if args.workload == "precision":
+        masks = torch.from_numpy(np.stack([T.disk_mask(64, 64, 24, inner=8),
+                                           T.standard_masks(64, 64, 0.25)[0]])).cuda()
     stream = torch.cuda.current_stream()
     plan = tacaw.Plan(spec.n_probe, spec.ny, spec.nx, spec.n_frames, L, H, masks=masks,
-                      transform=args.form, time_kernels=True, stream=stream)
+                      transform=args.form, in_dtype=spec.dtype, time_kernels=True, stream=stream)
     S = torch.empty((L, spec.ny, spec.nx), dtype=torch.float64, device="cuda")
     D = torch.empty((masks.shape[0], L), dtype=torch.float64, device="cuda")
     Dp = torch.empty((masks.shape[0], spec.n_probe, L), dtype=torch.float64, device="cuda")
@@ -165,6 +176,8 @@ def main():
     value = b_alg / (ms * 1e-3) / 1e9
     k_ms = float(np.mean(kernel_ms))
     achieved = b_alg / (k_ms * 1e-3) / 1e9
+    n_seg = plan.info()["n_segments"]
+    gemm_flops = 3 * 8 * L * L * n_seg * spec.n_probe * spec.n_k  # executed (3 split products)
     ksrc = os.path.join(ROOT, "paper_2607_02236_amd", "csrc",
                         "tacaw_fft.hip" if args.form == "fft" else "tacaw_gemm.hip")
     out = {
@@ -181,7 +194,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded generator: elastic 1 + 8 Lorentzian-line tones of 1e-3/sqrt(8) per pixel + 1e-5 noise)",
         "config": {
-            "workload": f"{spec.n_probe} probes x {spec.n_frames} frames x {spec.ny}x{spec.nx} complex64, "
+            "workload": f"{spec.n_probe} probes x {spec.n_frames} frames x {spec.ny}x{spec.nx} {spec.dtype}, "
                         f"Welch L={L} H={H} periodic Hann, global mean, {masks.shape[0]} detector masks, "
                         f"transform {args.form}",
             "probes": spec.n_probe, "frames": spec.n_frames, "ny": spec.ny, "nx": spec.nx,
@@ -189,7 +202,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "seg_fft_kernel" if args.form == "fft" else "seg_gemm_kernel",
+            "kernel": "seg_fft_kernel",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -198,6 +211,16 @@ def main():
             "traffic": traffic_from_profiles(ksrc),
         },
     }
+    if args.form != "fft":
+        tf = gemm_flops / (k_ms * 1e-3) / 1e12
+        out["dtype"] = "f16x3" if args.form == "gemm_f16x3" else "bf16x3"
+        out["roofline"] = {
+            "bound": "mfma", "kernel": "seg_gemm_kernel", "achieved": round(tf, 2),
+            "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4),
+            "kernel_ms": round(k_ms, 4), "traffic": None,
+            "note": "executed MFMA flops (3 split products of the 2L x 2L real GEMM per chunk); "
+                    "useful flops are one third",
+        }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         del psi

@@ -56,9 +56,12 @@ template <>
 struct FftShape<256> {
   static constexpr int N1 = 16, W = 16;
 };
+#ifndef TACAW_TILE_W512
+#define TACAW_TILE_W512 16  // pixels per workgroup at L = 512 (tuning parameter)
+#endif
 template <>
 struct FftShape<512> {
-  static constexpr int N1 = 16, W = 16;
+  static constexpr int N1 = 16, W = TACAW_TILE_W512;
 };
 template <>
 struct FftShape<1024> {
@@ -171,6 +174,18 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
   // of the last row (the host checks that this fits in 32 bits)
   const uint32_t group_bytes = (uint32_t)((int64_t)(N2 - 1) * row_bytes + (int64_t)n_k * ESZ);
 
+  // LEAN: raw samples of the next chunk, loaded one chunk ahead (software prefetch)
+  InT pre[LEAN ? N1 : 1];
+  auto fetch_at = [&](int ii, int ss, int n1) -> InT {
+    const char* rb = (const char*)a.in + (int64_t)ii * a.pstride * ESZ +
+                     ((int64_t)ss * H - a.push_begin + N2 * n1) * row_bytes;
+    return buffer_load<InT>(rb, group_bytes, lane_off);
+  };
+  if constexpr (LEAN) {
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) pre[n1] = fetch_at(0, a.s_lo, n1);
+  }
+
   for (int i = 0; i < a.n_probes; ++i) {
     const int p = a.probe0 + i;
     const double2 cr = a.cref[(int64_t)p * n_k + kc];
@@ -247,17 +262,30 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
 
       if constexpr (LEAN) {
         // chunk s: frames with t >= L/2 (n1 >= HALF) are new; t < L/2 are new only for s = 0
+        auto take_pre = [&](int lo, auto cmode) {
+#pragma unroll
+          for (int n1 = 0; n1 < N1; ++n1)
+            if (n1 >= lo) v[n1] = take(n1, pre[n1], cmode);
+        };
         if (have_kept) {
 #pragma unroll
           for (int n1 = 0; n1 < HALF; ++n1) v[n1] = kept[n1];
-          if (track) load_range(HALF, fetch_fast, C1{});
-          else load_range(HALF, fetch_fast, C0{});
+          if (track) take_pre(HALF, C1{});
+          else take_pre(HALF, C0{});
         } else if (!track) {
-          load_range(0, fetch_fast, C0{});
+          take_pre(0, C0{});
         } else if (s == 0) {
-          load_range(0, fetch_fast, C1{});
+          take_pre(0, C1{});
         } else {
-          load_range(0, fetch_fast, C3{});
+          take_pre(0, C3{});
+        }
+        // prefetch the next chunk's new samples (or the next probe's first chunk)
+        if (s + 1 < a.s_hi) {
+#pragma unroll
+          for (int n1 = HALF; n1 < N1; ++n1) pre[n1] = fetch_at(i, s + 1, n1);
+        } else if (i + 1 < a.n_probes) {
+#pragma unroll
+          for (int n1 = 0; n1 < N1; ++n1) pre[n1] = fetch_at(i + 1, a.s_lo, n1);
         }
       } else if (have_kept && half_hop) {
         // the kept half was counted in the previous chunk; the new half all counts

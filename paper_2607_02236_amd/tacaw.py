@@ -13,7 +13,7 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtacaw.so")
+LIB_PATH = os.environ.get("TACAW_LIB") or os.path.join(_HERE, "libtacaw.so")
 
 OK = 0
 ERR = {-1: "INVALID_ARG", -2: "SHAPE", -3: "STATE", -4: "OOM", -5: "HIP", -6: "UNSUPPORTED"}
@@ -213,6 +213,8 @@ class Plan:
     def backward(self, frames, probe0=0, gS=None, gD=None, gDp=None, grad=None, grad_wparam=None):
         """Adjoint: returns (grad_frames, dLoss/dwindow_param tensor of shape [1])."""
         frames, ps, fs = self._frames_args(frames)
+        if frames.shape[1] < self.info()["frames_used"]:
+            raise ValueError("backward needs every frame that enters a chunk (frames_used)")
         if grad is None:
             grad = torch.zeros_like(frames)
         if grad.stride() != frames.stride():
