@@ -121,29 +121,36 @@ hipError_t launch_ring_store(const void* in, int in_dtype, int64_t pstride, int6
   return hipGetLastError();
 }
 
-// Dp[d][probe0 + i][m] += sum_slot (part[slot][i][d][m] - part[slot][i-1][d][m]); the
-// partials hold cumulative sums over the launch's probes 0..i.
+// Per-probe detector spectra from the cumulative tile partials:
+// Dp[d][probe0 + i][m] += sum_slot (part[slot][i][d][m] - part[slot][i-1][d][m]).
+// Block (m-range, d, g) sums the slots of group g, reads every partial once and
+// adds its per-probe differences atomically (groups run in parallel).
+constexpr int kDpartGroups = 64;
 __global__ void dpart_reduce_kernel(const double* part, int32_t n_active, int32_t n_probes,
                                     int32_t n_det, int32_t L, int32_t probe0, int32_t n_probe_total,
                                     double* Dp) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   const int d = blockIdx.y;
-  const int i = blockIdx.z;
+  const int g = blockIdx.z;
   if (m >= L) return;
+  const int per = (n_active + kDpartGroups - 1) / kDpartGroups;
+  const int s0 = g * per, s1 = min(n_active, s0 + per);
+  if (s0 >= s1) return;
   const int64_t per_slot = (int64_t)n_probes * n_det * L;
-  double cur = 0.0, prev = 0.0;
-  for (int s = 0; s < n_active; ++s) {
-    const double* base = part + s * per_slot + (int64_t)d * L + m;
-    cur += base[(int64_t)i * n_det * L];
-    if (i > 0) prev += base[(int64_t)(i - 1) * n_det * L];
+  double prev = 0.0;
+  for (int i = 0; i < n_probes; ++i) {
+    const double* base = part + ((int64_t)i * n_det + d) * L + m;
+    double cur = 0.0;
+    for (int s = s0; s < s1; ++s) cur += base[s * per_slot];
+    atomicAdd(&Dp[((int64_t)d * n_probe_total + probe0 + i) * L + m], cur - prev);
+    prev = cur;
   }
-  Dp[((int64_t)d * n_probe_total + probe0 + i) * L + m] += cur - prev;
 }
 
 hipError_t launch_dpart_reduce(const double* dpart, int32_t n_active, int32_t n_probes,
                                int32_t n_det, int32_t L, int32_t probe0, int32_t n_probe_total,
                                double* Dp, hipStream_t st) {
-  dim3 g((L + 127) / 128, n_det, n_probes);
+  dim3 g((L + 127) / 128, n_det, kDpartGroups);
   hipLaunchKernelGGL(dpart_reduce_kernel, g, dim3(128), 0, st, dpart, n_active, n_probes, n_det,
                      L, probe0, n_probe_total, Dp);
   return hipGetLastError();
@@ -251,57 +258,65 @@ hipError_t launch_scale(double* p, int64_t n, double k, hipStream_t st) {
   return launch_finalize_S(p, nullptr, n, k, st);
 }
 
-// D[d][m] += sum over a pixel chunk of M_d(k) S(m, k); 8 bins per block.
-constexpr int kDetBins = 8;
-__global__ void detector_kernel(const double* S, const double* masks, int32_t n_det, int32_t L,
-                                int32_t n_k, int32_t chunk, double* D) {
+// D[d][m] += sum over a pixel chunk of M_d(k) S(m, k): each block takes kDetBins
+// bins and a chunk of pixels (coalesced rows of S), reduces across each wave
+// with lane shuffles and adds one value per (wave, bin, detector) atomically.
+constexpr int kDetBins = 4;
+template <int ND>
+__global__ void detector_kernel(const double* S, const double* masks, int32_t L, int32_t n_k,
+                                int32_t chunk, double* D) {
   const int m0 = blockIdx.y * kDetBins;
   const int64_t k0 = (int64_t)blockIdx.x * chunk;
   const int64_t k1 = (k0 + chunk < n_k) ? k0 + chunk : n_k;
-  double acc[kDetBins][kMaxDet];
+  double acc[kDetBins][ND];
 #pragma unroll
   for (int b = 0; b < kDetBins; ++b)
 #pragma unroll
-    for (int d = 0; d < kMaxDet; ++d) acc[b][d] = 0.0;
+    for (int d = 0; d < ND; ++d) acc[b][d] = 0.0;
   for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
-    double mk[kMaxDet];
+    double mk[ND];
 #pragma unroll
-    for (int d = 0; d < kMaxDet; ++d) mk[d] = (d < n_det) ? masks[(int64_t)d * n_k + k] : 0.0;
+    for (int d = 0; d < ND; ++d) mk[d] = masks[(int64_t)d * n_k + k];
 #pragma unroll
     for (int b = 0; b < kDetBins; ++b) {
-      if (m0 + b < L) {
-        const double s = S[(int64_t)(m0 + b) * n_k + k];
+      const double sv = (m0 + b < L) ? S[(int64_t)(m0 + b) * n_k + k] : 0.0;
 #pragma unroll
-        for (int d = 0; d < kMaxDet; ++d) acc[b][d] += mk[d] * s;
-      }
+      for (int d = 0; d < ND; ++d) acc[b][d] += mk[d] * sv;
     }
   }
-  __shared__ double red[256];
+#pragma unroll
   for (int b = 0; b < kDetBins; ++b) {
-    for (int d = 0; d < n_det; ++d) {
-      double v = 0.0;
 #pragma unroll
-      for (int bb = 0; bb < kDetBins; ++bb)
+    for (int d = 0; d < ND; ++d) {
+      double v = acc[b][d];
 #pragma unroll
-        for (int dd = 0; dd < kMaxDet; ++dd)
-          if (bb == b && dd == d) v = acc[bb][dd];
-      red[threadIdx.x] = v;
-      __syncthreads();
-      for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-      }
-      if (threadIdx.x == 0 && m0 + b < L) atomicAdd(&D[(int64_t)d * L + m0 + b], red[0]);
-      __syncthreads();
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if ((threadIdx.x & 63) == 0 && m0 + b < L) atomicAdd(&D[(int64_t)d * L + m0 + b], v);
     }
   }
 }
 
+template <int ND>
+static void launch_det_nd(const double* S, const double* masks, int32_t L, int32_t n_k,
+                          double* D, hipStream_t st) {
+  const int chunk = 16384;
+  dim3 g((n_k + chunk - 1) / chunk, (L + kDetBins - 1) / kDetBins);
+  hipLaunchKernelGGL((detector_kernel<ND>), g, dim3(256), 0, st, S, masks, L, n_k, chunk, D);
+}
+
 hipError_t launch_detector(const double* S, const double* masks, int32_t n_det, int32_t L,
                            int32_t n_k, double* D, hipStream_t st) {
-  const int chunk = 8192;
-  dim3 g((n_k + chunk - 1) / chunk, (L + kDetBins - 1) / kDetBins);
-  hipLaunchKernelGGL(detector_kernel, g, dim3(256), 0, st, S, masks, n_det, L, n_k, chunk, D);
+  switch (n_det) {
+    case 1: launch_det_nd<1>(S, masks, L, n_k, D, st); break;
+    case 2: launch_det_nd<2>(S, masks, L, n_k, D, st); break;
+    case 3: launch_det_nd<3>(S, masks, L, n_k, D, st); break;
+    case 4: launch_det_nd<4>(S, masks, L, n_k, D, st); break;
+    case 5: launch_det_nd<5>(S, masks, L, n_k, D, st); break;
+    case 6: launch_det_nd<6>(S, masks, L, n_k, D, st); break;
+    case 7: launch_det_nd<7>(S, masks, L, n_k, D, st); break;
+    case 8: launch_det_nd<8>(S, masks, L, n_k, D, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -123,7 +123,10 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
   static_assert(N1 % N2 == 0 || N2 % N1 == 0, "pass-2 split");
   static_assert(G == 1 || G == 2 || G == 4, "pass-2 split factor");
 
-  __shared__ float2 xbuf[N1 * KROW];  // exchange tile [k1][n2][px]; reused for reductions
+  // two exchange tiles [k1][n2][px] used by alternate chunks, so one barrier per
+  // chunk suffices; tile 0 is reused for the per-probe reductions
+  __shared__ float2 xbuf2[2 * N1 * KROW];
+  float2* const xbuf = xbuf2;
   __shared__ float2 s_tw[L];          // [n2][k1]
   __shared__ float s_win[L];          // [n2][n1]
   __shared__ double s_mask[DP ? kMaxDet * W : 1];
@@ -186,6 +189,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
     for (int n1 = 0; n1 < N1; ++n1) pre[n1] = fetch_at(0, a.s_lo, n1);
   }
 
+  int cc = 0;  // chunks processed by this thread block (selects the exchange tile)
   for (int i = 0; i < a.n_probes; ++i) {
     const int p = a.probe0 + i;
     const double2 cr = a.cref[(int64_t)p * n_k + kc];
@@ -326,9 +330,13 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
 #pragma unroll
       for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], s_tw[n2 * N1 + k1]);
 
-      __syncthreads();  // previous chunk's pass-2 reads are complete
+      // tile (cc & 1), cc counting this thread block's chunks: the reads of
+      // chunk cc - 2 from it finished before the barrier of chunk cc - 1, so only
+      // the barrier after the writes is needed
+      float2* const xb = xbuf2 + (cc & 1) * (N1 * KROW);
+      ++cc;
 #pragma unroll
-      for (int k1 = 0; k1 < N1; ++k1) xbuf[k1 * KROW + n2 * W + px] = v[k1];
+      for (int k1 = 0; k1 < N1; ++k1) xb[k1 * KROW + n2 * W + px] = v[k1];
       __syncthreads();
 
       if constexpr (G == 1) {
@@ -336,7 +344,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
 #pragma unroll
         for (int q = 0; q < R; ++q) {
           float2 X[N2];
-          const float2* col = xbuf + (j + N2 * q) * KROW + px;
+          const float2* col = xb + (j + N2 * q) * KROW + px;
 #pragma unroll
           for (int r = 0; r < N2; ++r) X[r] = col[r * W];
           dft_inplace<N2>(X);
@@ -358,7 +366,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
         }
       } else {
         // G-mode: G threads share the N2-point DFT of k1 = j % N1
-        const float2* col = xbuf + k1g * KROW + px;
+        const float2* col = xb + k1g * KROW + px;
         float2 X[N1];
         if constexpr (G == 2) {
           if (gg == 0) dif_combine<N1, 2, 0>(col, W, X);
@@ -415,8 +423,8 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
     }
 
     if constexpr (DP) {
-      // per-probe detector partials of the cumulative sum over this launch's
-      // probes 0..i (the reduce kernel differences consecutive probes)
+      // detector partials: the mask-weighted tile sum of the FP64 accumulator,
+      // cumulative over this launch's probes (the reduce kernel differences them)
       __syncthreads();
       double* sp = reinterpret_cast<double*>(xbuf);  // [L][W]
 #pragma unroll
@@ -437,11 +445,13 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
             double dsum = 0.0;
 #pragma unroll
             for (int x = 0; x < W; ++x) dsum += s_mask[d * W + x] * pv[x];
-            out[(int64_t)d * L + m] = dsum;
+            out[(int64_t)d * L + m] = dsum;  // cumulative over the launch's probes 0..i
           }
         }
       }
     }
+    // the reductions above used tile 0, which a later chunk writes
+    __syncthreads();
   }
 
   if (kvalid) {

@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
     }
 
     if constexpr (DP) {
-      // cumulative per-probe detector partials through LDS, two halves of the bins
+      // cumulative detector partials through LDS, two halves of the bins
       double* sd = reinterpret_cast<double*>(bst);  // needs L/2 * 32 doubles
       static_assert(sizeof(bst) >= (size_t)L / 2 * kGemmPx * 8, "LDS for partials");
       const int slot = a.tile_slot[tile];
@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
               double dsum = 0.0;
 #pragma unroll
               for (int x = 0; x < kGemmPx; ++x) dsum += s_mask[d * kGemmPx + x] * sd[mm * kGemmPx + x];
-              out[(int64_t)d * L + hb * (L / 2) + mm] = dsum;
+              out[(int64_t)d * L + hb * (L / 2) + mm] = dsum;  // cumulative over probes 0..i
             }
           }
         }
