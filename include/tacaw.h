@@ -47,6 +47,9 @@ extern "C" {
 #define TACAW_WIN_HANN_WIDTH 2 /* width-r Hann: 1/2 + 1/2 cos(2 pi (t - L/2)/(r L))    */
                                /* for |t - L/2| <= r L / 2, else 0; r = window_param  */
 #define TACAW_WIN_TUKEY 3      /* periodic Tukey, window_param = alpha (taper share)  */
+#define TACAW_WIN_CUSTOM 4     /* caller-supplied values h_window[0..L-1] (e.g. the   */
+                               /* Blackman-Harris, Kaiser and Dolph-Chebyshev windows */
+                               /* of App. A)                                          */
 
 /* ---- elastic-mean handling (the mean is removed before the window) ------ */
 #define TACAW_MEAN_GLOBAL 0      /* mean over the frames that enter a chunk (default) */
@@ -92,6 +95,12 @@ typedef struct {
   int32_t max_probes_in_flight; /* probes with a partially pushed series at once    */
                                 /* (streaming ring capacity); 0 = n_probe            */
   int32_t flags;          /* TACAW_FLAG_* bits                                       */
+  double temperature_K;   /* > 0: multiply bin m by the quantum-statistics factor    */
+                          /* beta E_m / (1 - exp(-beta E_m)) of Eq. 1, beta = 1/kT,  */
+                          /* E_m = h nu_m (dt_fs sets nu_m; +nu is energy loss);     */
+                          /* 0: no factor                                            */
+  const double* h_window; /* host array of seg_len window values (TACAW_WIN_CUSTOM)  */
+                          /* copied at plan creation; NULL otherwise                 */
 } tacaw_plan_desc;
 
 /* flags: record HIP events around the chunk kernel of every push; the last

@@ -94,6 +94,7 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
         if (a.gDp) c += a.kappa_p * a.gDp[((int64_t)d * a.n_probe_total + p) * L + m];
         g += c * (double)mk[d];
       }
+      if (a.qfac) g *= a.qfac[m];
       Gt[t] = (float)g;
     }
     const double2 mu = a.mu ? a.mu[(int64_t)p * n_k + kc] : make_double2(0.0, 0.0);

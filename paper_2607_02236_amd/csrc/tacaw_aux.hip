@@ -237,25 +237,27 @@ hipError_t launch_correct_Dp(const CorrArgs& c, const double* masks, int32_t n_d
   return hipGetLastError();
 }
 
-// out = in * kappa (in place when out == in)
-__global__ void scale_copy_kernel(double* S, double* out, int64_t n, double kappa) {
+// S[i] <- kappa q(m) S[i], m = (i / inner) % L (q null: factor 1); copy to out if given
+__global__ void scale_copy_kernel(double* S, double* out, int64_t n, double kappa, const double* q,
+                                  int64_t inner, int32_t L) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const double v = S[i] * kappa;
+    const double f = q ? kappa * q[(i / inner) % L] : kappa;
+    const double v = S[i] * f;
     S[i] = v;
     if (out) out[i] = v;
   }
 }
 
-hipError_t launch_finalize_S(double* S, double* out, int64_t n_elem, double kappa,
-                             hipStream_t st) {
+hipError_t launch_finalize_S(double* S, double* out, int64_t n_elem, double kappa, const double* q,
+                             int64_t inner, int32_t L, hipStream_t st) {
   hipLaunchKernelGGL(scale_copy_kernel, dim3(blocks_for(n_elem, 256, 8192)), dim3(256), 0, st, S,
-                     out, n_elem, kappa);
+                     out, n_elem, kappa, q, inner, L);
   return hipGetLastError();
 }
 
 hipError_t launch_scale(double* p, int64_t n, double k, hipStream_t st) {
-  return launch_finalize_S(p, nullptr, n, k, st);
+  return launch_finalize_S(p, nullptr, n, k, nullptr, 1, 1, st);
 }
 
 // D[d][m] += sum over a pixel chunk of M_d(k) S(m, k): each block takes kDetBins

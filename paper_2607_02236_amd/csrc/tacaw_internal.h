@@ -78,7 +78,9 @@ struct CorrArgs {
   const double2* msum;
   const double2* xs;
 };
-hipError_t launch_finalize_S(double* S, double* out, int64_t n_elem, double kappa, hipStream_t st);
+// S[i] <- kappa * q[(i / inner) % L] * S[i] (q may be null), copied to out when given
+hipError_t launch_finalize_S(double* S, double* out, int64_t n_elem, double kappa, const double* q,
+                             int64_t inner, int32_t L, hipStream_t st);
 hipError_t launch_correct_S(const CorrArgs& c, double* S, double* out, double kappa, hipStream_t st);
 hipError_t launch_correct_Dp(const CorrArgs& c, const double* masks, int32_t n_det, double* Dp,
                              hipStream_t st);
@@ -105,6 +107,7 @@ struct BwdArgs {
   const double* gDp;       // [n_det][n_probe][L] or null
   const double* masks;     // [n_det][n_k]
   double kappa_S, kappa_p; // normalisations of S and S_p
+  const double* qfac;      // [L] quantum-statistics factor or null
   double2* gmean;          // [n_probes][n_k] sum over chunks and t of w * grad_y (mean term)
   double* dwpart;          // [n_tiles][2] partial sums: r-derivative term, loss value
 };

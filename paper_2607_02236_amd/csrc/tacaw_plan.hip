@@ -186,6 +186,7 @@ struct tacaw_plan_s {
   double* scratch = nullptr;
   int64_t scratch_bytes = 0;
   float* gscale = nullptr;  // GEMM form: [P][n_k]
+  double* qfac = nullptr;   // [L] quantum-statistics factor per bin (temperature > 0)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
 
@@ -259,8 +260,11 @@ int tacaw_plan_check(const tacaw_plan_desc* d) {
     return fail(TACAW_ERR_INVALID_ARG, "hop must satisfy 1 <= hop <= seg_len");
   if (d->n_frames < d->seg_len)
     return fail(TACAW_ERR_INVALID_ARG, "n_frames must be >= seg_len (at least one full chunk)");
-  if (d->window < TACAW_WIN_HANN || d->window > TACAW_WIN_TUKEY)
+  if (d->window < TACAW_WIN_HANN || d->window > TACAW_WIN_CUSTOM)
     return fail(TACAW_ERR_INVALID_ARG, "unknown window");
+  if (d->window == TACAW_WIN_CUSTOM && !d->h_window)
+    return fail(TACAW_ERR_INVALID_ARG, "CUSTOM window needs h_window");
+  if (!(d->temperature_K >= 0.0)) return fail(TACAW_ERR_INVALID_ARG, "temperature_K must be >= 0");
   if (d->window == TACAW_WIN_HANN_WIDTH && !(d->window_param > 0.0 && d->window_param <= 4.0))
     return fail(TACAW_ERR_INVALID_ARG, "HANN_WIDTH needs 0 < window_param <= 4");
   if (d->window == TACAW_WIN_TUKEY && !(d->window_param >= 0.0 && d->window_param <= 1.0))
@@ -311,7 +315,8 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   P->slot_owner.assign(P->n_slots, -1);
 
   // window, its DFT at every bin (FP64), and the correction bins
-  const std::vector<double> w = make_window(d->window, P->L, d->window_param);
+  std::vector<double> w = make_window(d->window, P->L, d->window_param);
+  if (d->window == TACAW_WIN_CUSTOM) w.assign(d->h_window, d->h_window + P->L);
   P->sumw2 = 0.0;
   double sumw = 0.0;
   for (double x : w) {
@@ -387,6 +392,7 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   A((void**)&P->xs, np * kMaxCorr * nk * 16, "correction sums");
   A((void**)&P->S, (int64_t)P->L * nk * 8, "spectrum accumulator");
   A((void**)&P->scratch, 64, "scratch");
+  if (d->temperature_K > 0.0) A((void**)&P->qfac, (int64_t)P->L * 8, "quantum factor");
   if (gemm) {
     A(&P->fmat, (int64_t)2 * (2 * P->L) * (2 * P->L) * 2, "DFT matrix");
     A((void**)&P->gscale, np * nk * 4, "operand scales");
@@ -406,6 +412,19 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   H2D(P->win_t, wt.data(), P->L * 4);
   H2D(P->dwin_t, dwt.data(), P->L * 4);
   H2D(P->tw, twt.data(), P->L * 8);
+  if (P->qfac && rc == TACAW_OK) {
+    // E_m = h nu_m, nu_m = m / (L dt) (m < L/2) or (m - L) / (L dt); factor x / (1 - e^-x),
+    // x = E_m / (k_B T), limit 1 at E = 0
+    const double h_ev_s = 6.62607015e-34 / 1.602176634e-19, kb_ev_k = 8.617333262e-5;
+    std::vector<double> q(P->L);
+    for (int m = 0; m < P->L; ++m) {
+      const int sm = m < (P->L + 1) / 2 ? m : m - P->L;
+      const double e = h_ev_s * (double)sm / ((double)P->L * d->dt_fs * 1e-15);
+      const double x = e / (kb_ev_k * d->temperature_K);
+      q[m] = x == 0.0 ? 1.0 : x / (-std::expm1(-x));
+    }
+    H2D(P->qfac, q.data(), (int64_t)P->L * 8);
+  }
   if (gemm && rc == TACAW_OK) {
     const std::vector<uint16_t> fm = make_dft_matrix(w, d->transform == TACAW_GEMM_F16X3);
     H2D(P->fmat, fm.data(), (int64_t)fm.size() * 2);
@@ -674,10 +693,12 @@ int tacaw_finalize(tacaw_plan_t P, double* d_S) {
     if (P->d.n_det > 0)
       TRY(hip_check(launch_correct_Dp(c, P->masks, P->d.n_det, P->Dp, P->st), "mean correction"));
   }
-  TRY(hip_check(launch_finalize_S(P->S, d_S, (int64_t)P->L * P->n_k, kappa_S(P), P->st),
+  TRY(hip_check(launch_finalize_S(P->S, d_S, (int64_t)P->L * P->n_k, kappa_S(P), P->qfac,
+                                  P->n_k, P->L, P->st),
                 "normalisation"));
   if (P->d.n_det > 0)
-    TRY(hip_check(launch_scale(P->Dp, (int64_t)P->d.n_det * P->d.n_probe * P->L, kappa_probe(P), P->st),
+    TRY(hip_check(launch_finalize_S(P->Dp, nullptr, (int64_t)P->d.n_det * P->d.n_probe * P->L,
+                                    kappa_probe(P), P->qfac, 1, P->L, P->st),
                   "normalisation"));
   P->state = 1;
   return TACAW_OK;
@@ -769,6 +790,7 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   b.masks = P->masks;
   b.kappa_S = kappa_S(P);
   b.kappa_p = kappa_probe(P);
+  b.qfac = P->qfac;
   b.gmean = (double2*)P->scratch;
   b.dwpart = P->scratch + (int64_t)n_probes * P->n_k * 2;
   TRY(hip_check(launch_bwd(P->L, P->d.in_dtype, b, n_tiles, P->st), "adjoint kernel"));

@@ -17,7 +17,7 @@ LIB_PATH = os.environ.get("TACAW_LIB") or os.path.join(_HERE, "libtacaw.so")
 
 OK = 0
 ERR = {-1: "INVALID_ARG", -2: "SHAPE", -3: "STATE", -4: "OOM", -5: "HIP", -6: "UNSUPPORTED"}
-WINDOWS = {"hann": 0, "rect": 1, "hann_width": 2, "tukey": 3}
+WINDOWS = {"hann": 0, "rect": 1, "hann_width": 2, "tukey": 3, "custom": 4}
 MEANS = {"global": 0, "per_segment": 1, "none": 2}
 TRANSFORMS = {"fft": 0, "gemm_bf16x3": 1, "gemm_f16x3": 2}
 DTYPES = {"c64": 0, "c128": 1}
@@ -41,6 +41,7 @@ class PlanDesc(C.Structure):
         ("probe_reduce", C.c_int32), ("dt_fs", C.c_double),
         ("n_det", C.c_int32), ("d_masks", C.c_void_p),
         ("max_probes_in_flight", C.c_int32), ("flags", C.c_int32),
+        ("temperature_K", C.c_double), ("h_window", C.c_void_p),
     ]
 
 
@@ -93,12 +94,24 @@ def _check(rc):
 
 def make_desc(n_probe, ny, nx, n_frames, seg_len, hop, window="hann", window_param=1.0,
               mean_mode="global", transform="fft", in_dtype="c64", probe_reduce="mean",
-              dt_fs=5.0, n_det=0, masks_ptr=0, max_probes_in_flight=0, flags=0) -> PlanDesc:
-    return PlanDesc(int(n_probe), int(ny), int(nx), int(n_frames), int(seg_len), int(hop),
-                    WINDOWS[window], float(window_param), MEANS[mean_mode],
-                    TRANSFORMS[transform], DTYPES[in_dtype], REDUCE[probe_reduce],
-                    float(dt_fs), int(n_det), C.c_void_p(masks_ptr or None),
-                    int(max_probes_in_flight), int(flags))
+              dt_fs=5.0, n_det=0, masks_ptr=0, max_probes_in_flight=0, flags=0,
+              temperature_K=0.0, window_values=None) -> PlanDesc:
+    """window may be a name or an array of seg_len values (custom window)."""
+    wptr = None
+    if not isinstance(window, str):
+        import numpy as np
+
+        vals = np.ascontiguousarray(np.asarray(window, dtype=np.float64))
+        window, window_values = "custom", vals
+    if window_values is not None:
+        wptr = window_values.ctypes.data
+    d = PlanDesc(int(n_probe), int(ny), int(nx), int(n_frames), int(seg_len), int(hop),
+                 WINDOWS[window], float(window_param), MEANS[mean_mode],
+                 TRANSFORMS[transform], DTYPES[in_dtype], REDUCE[probe_reduce],
+                 float(dt_fs), int(n_det), C.c_void_p(masks_ptr or None),
+                 int(max_probes_in_flight), int(flags), float(temperature_K), C.c_void_p(wptr))
+    d._window_values = window_values  # keep the host array alive with the descriptor
+    return d
 
 
 def check_desc(**kw) -> None:
@@ -123,7 +136,7 @@ class Plan:
     def __init__(self, n_probe, ny, nx, n_frames, seg_len, hop=None, window="hann",
                  window_param=1.0, mean_mode="global", transform="fft", in_dtype="c64",
                  probe_reduce="mean", dt_fs=5.0, masks=None, max_probes_in_flight=0,
-                 stream=None, time_kernels=False):
+                 stream=None, time_kernels=False, temperature_K=0.0):
         self.handle = None
         hop = seg_len // 2 if hop is None else hop
         self.n_probe, self.ny, self.nx = int(n_probe), int(ny), int(nx)
@@ -144,7 +157,7 @@ class Plan:
         self.stream, sptr = _stream_ptr(stream)
         self.desc = make_desc(n_probe, ny, nx, n_frames, seg_len, hop, window, window_param,
                               mean_mode, transform, in_dtype, probe_reduce, dt_fs, n_det, mptr,
-                              max_probes_in_flight, 1 if time_kernels else 0)
+                              max_probes_in_flight, 1 if time_kernels else 0, temperature_K)
         h = C.c_void_p()
         _check(lib.tacaw_plan(C.byref(self.desc), sptr, C.byref(h)))
         self.handle = h

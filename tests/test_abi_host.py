@@ -54,6 +54,9 @@ def _ok(**over):
     (dict(n_det=2), "INVALID_ARG"),
     (dict(max_probes_in_flight=3), "INVALID_ARG"),
     (dict(ny=1 << 16, nx=1 << 16), "INVALID_ARG"),
+    (dict(window="custom"), "INVALID_ARG"),
+    (dict(temperature_K=-1.0), "INVALID_ARG"),
+    (dict(transform="gemm_f16x3", seg_len=1024, n_frames=2048, hop=512), "UNSUPPORTED"),
 ])
 def test_descriptor_validation_errors(over, kind):
     from paper_2607_02236_amd import tacaw
@@ -70,6 +73,10 @@ def test_valid_descriptors_pass():
     tacaw.check_desc(**_ok())
     tacaw.check_desc(**_ok(window="rect", mean_mode="none", in_dtype="c128", probe_reduce="sum"))
     tacaw.check_desc(**_ok(seg_len=1024, n_frames=4096, hop=512, max_probes_in_flight=1))
+    import numpy as np
+
+    tacaw.check_desc(**_ok(window=np.hanning(128), temperature_K=300.0))
+    tacaw.check_desc(**_ok(transform="gemm_bf16x3"))
 
 
 def test_null_arguments_are_rejected_without_a_device():

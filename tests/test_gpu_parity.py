@@ -244,3 +244,41 @@ def test_generator_is_bit_identical_on_gpu():
     assert torch.equal(a, b)
     spec = T.config_plain_1probe()
     assert torch.equal(T.generate(spec, frames=(0, 32), device="cuda").cpu(), T.generate(spec, frames=(0, 32)))
+
+
+@pytest.mark.parametrize("name,param", [
+    ("blackmanharris", None), (("kaiser", 3 * np.pi), None), (("kaiser", 5 * np.pi), None),
+    (("chebwin", 100), None),
+])
+def test_custom_windows_from_appendix(tacaw, name, param):
+    # App. A compares Kaiser (beta 3 pi, 5 pi), Dolph-Chebyshev (100 dB) and
+    # Blackman-Harris windows; the library takes any window as an array
+    import scipy.signal
+
+    L, H = 256, 128
+    w = scipy.signal.get_window(name, L)  # periodic (DFT-even) form
+    spec = T.SeriesSpec(2, 640, 8, 10, dtype="c64", seed=17, model="lines", n_terms=8)
+    psi = T.generate(spec)
+    masks = T.standard_masks(8, 10, scale=0.06)
+    g = run_gpu(tacaw, psi, L, H, masks, window=w)
+    S, Sp = O.tacaw_spectra(psi.numpy(), L, H, w)
+    o = {"S": S, "D": O.detector_spectra(S, masks),
+         "Dp": np.transpose(O.detector_spectra(Sp, masks), (1, 0, 2))}
+    check(g, o, label=f"window {name}")
+
+
+@pytest.mark.parametrize("T_K", [300.0, 50.0])
+def test_quantum_statistics_factor(tacaw, T_K):
+    # Eq. 1: I(q, E) ~ beta E / (1 - exp(-beta E)) |phi(q, E)|^2
+    L, H, dt = 256, 128, 5.0
+    spec = T.SeriesSpec(2, 512, 8, 8, dtype="c64", seed=23, model="lines", n_terms=8)
+    psi = T.generate(spec)
+    masks = T.standard_masks(8, 8, scale=0.05)
+    g = run_gpu(tacaw, psi, L, H, masks, temperature_K=T_K, dt_fs=dt)
+    q = O.quantum_factor(O.energy_axis_mev(L, dt), T_K)
+    S, Sp = O.tacaw_spectra(psi.numpy(), L, H, O.window("hann", L))
+    S = S * q[:, None]
+    Sp = Sp * q[None, :, None]
+    o = {"S": S, "D": O.detector_spectra(S, masks),
+         "Dp": np.transpose(O.detector_spectra(Sp, masks), (1, 0, 2))}
+    check(g, o, label=f"quantum factor T={T_K}")
