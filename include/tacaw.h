@@ -13,7 +13,9 @@
  *  - Frequency bins are in FFT order: bin m holds nu_m = m / (L dt) for
  *    m < L/2 and (m - L) / (L dt) otherwise; the forward kernel is
  *    exp(-2 pi i m t / L) (Sec. III.B transform sign), so exp(+2 pi i nu t)
- *    lands at +nu.
+ *    lands at +nu. A plan with an energy window (omega_half = M > 0) keeps only
+ *    the bins of signed index -M..M, in ascending order (row r = M + signed m).
+ *    "n_omega" below is the number of output bins, L or 2M + 1.
  *  - All device pointers are caller-owned HIP device memory (e.g. torch
  *    tensors) unless stated otherwise. Work is enqueued on the plan's HIP
  *    stream in call order; an input buffer must stay alive until the stream has
@@ -101,6 +103,12 @@ typedef struct {
                           /* 0: no factor                                            */
   const double* h_window; /* host array of seg_len window values (TACAW_WIN_CUSTOM)  */
                           /* copied at plan creation; NULL otherwise                 */
+  int32_t omega_half;     /* energy window (the centred +-ROI of Sec. II.B / App. B):*/
+                          /* 0 = all seg_len bins in FFT order; M in [1, L/2 - 1] =  */
+                          /* only the 2M + 1 bins of signed index -M..M (frequency   */
+                          /* m / (L dt)), stored in ascending order, row r = m + M.  */
+                          /* S, D, D_p and their gradients then have n_omega = 2M+1  */
+                          /* rows, and the DFT-GEMM form computes only these rows.   */
 } tacaw_plan_desc;
 
 /* flags: record HIP events around the chunk kernel of every push; the last
@@ -110,7 +118,7 @@ typedef struct {
 
 typedef struct {
   int32_t n_segments;     /* N_s                                                     */
-  int32_t n_omega;        /* frequency bins (= seg_len)                              */
+  int32_t n_omega;        /* output bins: seg_len, or 2 omega_half + 1               */
   int64_t frames_used;    /* (N_s - 1) * hop + seg_len                               */
   int64_t frames_dropped; /* frames pushed so far beyond frames_used (all probes)    */
   int64_t device_bytes;   /* device memory currently owned by the plan               */

@@ -15,14 +15,16 @@ from . import tacaw
 
 class TacawSpectra(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, frames, window_param, masks, seg_len, hop, window, mean_mode, probe_reduce):
+    def forward(ctx, frames, window_param, masks, seg_len, hop, window, mean_mode, probe_reduce,
+                omega_half, temperature_K, dt_fs):
         if frames.dim() == 3:
             frames = frames[None]
         P, NT, ny, nx = frames.shape
         in_dtype = "c64" if frames.dtype == torch.complex64 else "c128"
         plan = tacaw.Plan(P, ny, nx, NT, seg_len, hop, window=window,
                           window_param=float(window_param), mean_mode=mean_mode,
-                          in_dtype=in_dtype, probe_reduce=probe_reduce, masks=masks)
+                          in_dtype=in_dtype, probe_reduce=probe_reduce, masks=masks,
+                          omega_half=omega_half, temperature_K=temperature_K, dt_fs=dt_fs)
         plan.push(frames.detach())
         S = plan.finalize()
         if masks is not None:
@@ -45,16 +47,18 @@ class TacawSpectra(torch.autograd.Function):
                                  gDp=gDp if ctx.has_masks else None)
         plan.close()
         ctx.plan = None
-        return grad, gw.reshape(()), None, None, None, None, None, None
+        return grad, gw.reshape(()), None, None, None, None, None, None, None, None, None
 
 
 def spectra(frames, seg_len, hop=None, masks=None, window="hann", window_param=1.0,
-            mean_mode="global", probe_reduce="mean"):
-    """Differentiable (S, D, D_p); window_param may be a float64 tensor with requires_grad."""
+            mean_mode="global", probe_reduce="mean", omega_half=0, temperature_K=0.0,
+            dt_fs=5.0):
+    """Differentiable (S, D, D_p); window_param may be a float64 tensor with requires_grad.
+    omega_half and temperature_K as in tacaw.Plan (energy window, quantum factor)."""
     hop = seg_len // 2 if hop is None else hop
     if not torch.is_tensor(window_param):
         window_param = torch.tensor(float(window_param), dtype=torch.float64, device=frames.device)
     if masks is not None:
         masks = masks.to(device=frames.device, dtype=torch.float64)
     return TacawSpectra.apply(frames, window_param, masks, seg_len, hop, window, mean_mode,
-                              probe_reduce)
+                              probe_reduce, int(omega_half), float(temperature_K), float(dt_fs))

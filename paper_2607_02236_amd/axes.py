@@ -36,3 +36,20 @@ def roi_bins(seg_len, dt_fs, f_max_thz):
     m = np.arange(seg_len)
     signed = np.where(m < (seg_len + 1) // 2, m, m - seg_len)
     return np.nonzero(np.abs(signed) <= np.floor(f_max_thz / step + 1e-9))[0]
+
+
+def omega_half_for(seg_len, dt_fs, f_max_thz=None, e_max_mev=None):
+    """Energy-window half width M (bins) for |nu| <= f_max_thz or |E| <= e_max_mev:
+    the largest M with M / (L dt) within the limit, capped at L/2 - 1."""
+    step_thz = 1.0 / (seg_len * dt_fs * 1e-15) / 1e12
+    if f_max_thz is None:
+        f_max_thz = e_max_mev * 1e-3 / PLANCK_EV_S / 1e12
+    return int(min(seg_len // 2 - 1, np.floor(f_max_thz / step_thz + 1e-9)))
+
+
+def window_rows(seg_len, omega_half):
+    """FFT-order bin of every output row: all bins (omega_half = 0) or the
+    ascending bins -M..M of an energy window."""
+    if omega_half == 0:
+        return np.arange(seg_len)
+    return np.mod(np.arange(-omega_half, omega_half + 1), seg_len)

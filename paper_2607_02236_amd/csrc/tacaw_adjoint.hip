@@ -82,19 +82,23 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
   for (int i = 0; i < a.n_probes; ++i) {
     const int p = a.probe0 + i;
     // upstream weight for the thread's bins
+    // (bins outside the energy window have no output row and weight 0)
     float Gt[N1];
 #pragma unroll
     for (int t = 0; t < N1; ++t) {
-      const int m = F::bin(t, n2);
+      const int r = (F::bin(t, n2) + a.roi_half) & (L - 1);  // output row of the bin
+      const int n_om = a.n_om;
       double g = 0.0;
-      if (a.gS) g += a.kappa_S * a.gS[(int64_t)m * n_k + kc];
-      for (int d = 0; d < a.n_det; ++d) {
-        double c = 0.0;
-        if (a.gD) c += a.kappa_S * a.gD[(int64_t)d * L + m];
-        if (a.gDp) c += a.kappa_p * a.gDp[((int64_t)d * a.n_probe_total + p) * L + m];
-        g += c * (double)mk[d];
+      if (r < n_om) {
+        if (a.gS) g += a.kappa_S * a.gS[(int64_t)r * n_k + kc];
+        for (int d = 0; d < a.n_det; ++d) {
+          double c = 0.0;
+          if (a.gD) c += a.kappa_S * a.gD[(int64_t)d * n_om + r];
+          if (a.gDp) c += a.kappa_p * a.gDp[((int64_t)d * a.n_probe_total + p) * n_om + r];
+          g += c * (double)mk[d];
+        }
+        if (a.qfac) g *= a.qfac[r];
       }
-      if (a.qfac) g *= a.qfac[m];
       Gt[t] = (float)g;
     }
     const double2 mu = a.mu ? a.mu[(int64_t)p * n_k + kc] : make_double2(0.0, 0.0);

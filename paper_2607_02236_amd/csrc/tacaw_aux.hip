@@ -182,7 +182,7 @@ __global__ void correct_S_kernel(const CorrArgs c, double* S) {
   for (int b = 0; b < c.n_corr; ++b) {
     double sum = 0.0;
     for (int p = 0; p < c.n_probe; ++p) sum += corr_term(c, p, k, b);
-    S[(int64_t)c.bins[b] * c.n_k + k] += sum;
+    S[(int64_t)c.rows[b] * c.n_k + k] += sum;
   }
 }
 
@@ -223,7 +223,7 @@ __global__ void correct_Dp_kernel(const CorrArgs c, const double* masks, int32_t
         __syncthreads();
       }
       if (threadIdx.x == 0)
-        atomicAdd(&Dp[((int64_t)d * c.n_probe + p) * c.L + c.bins[b]], red[0]);
+        atomicAdd(&Dp[((int64_t)d * c.n_probe + p) * c.n_om + c.rows[b]], red[0]);
       __syncthreads();
     }
   }
@@ -237,12 +237,12 @@ hipError_t launch_correct_Dp(const CorrArgs& c, const double* masks, int32_t n_d
   return hipGetLastError();
 }
 
-// S[i] <- kappa q(m) S[i], m = (i / inner) % L (q null: factor 1); copy to out if given
+// S[i] <- kappa q(r) S[i], row r = (i / inner) % n_om (q null: factor 1); copy to out if given
 __global__ void scale_copy_kernel(double* S, double* out, int64_t n, double kappa, const double* q,
-                                  int64_t inner, int32_t L) {
+                                  int64_t inner, int32_t n_om) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const double f = q ? kappa * q[(i / inner) % L] : kappa;
+    const double f = q ? kappa * q[(i / inner) % n_om] : kappa;
     const double v = S[i] * f;
     S[i] = v;
     if (out) out[i] = v;
@@ -250,9 +250,9 @@ __global__ void scale_copy_kernel(double* S, double* out, int64_t n, double kapp
 }
 
 hipError_t launch_finalize_S(double* S, double* out, int64_t n_elem, double kappa, const double* q,
-                             int64_t inner, int32_t L, hipStream_t st) {
+                             int64_t inner, int32_t n_om, hipStream_t st) {
   hipLaunchKernelGGL(scale_copy_kernel, dim3(blocks_for(n_elem, 256, 8192)), dim3(256), 0, st, S,
-                     out, n_elem, kappa, q, inner, L);
+                     out, n_elem, kappa, q, inner, n_om);
   return hipGetLastError();
 }
 

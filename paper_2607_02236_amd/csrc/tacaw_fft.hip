@@ -435,8 +435,10 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
       __syncthreads();
       const int slot = a.tile_slot[tile];
       if (slot >= 0) {
-        double* out = a.dpart + ((int64_t)slot * a.n_probes + i) * a.n_det * L;
-        for (int m = tid; m < L; m += NT) {
+        const int n_om = a.n_om;
+        double* out = a.dpart + ((int64_t)slot * a.n_probes + i) * a.n_det * n_om;
+        for (int r = tid; r < n_om; r += NT) {
+          const int m = (r - a.roi_half) & (L - 1);  // output row r holds bin m
           double pv[W];
 #pragma unroll
           for (int x = 0; x < W; ++x) pv[x] = sp[m * W + x];
@@ -445,7 +447,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
             double dsum = 0.0;
 #pragma unroll
             for (int x = 0; x < W; ++x) dsum += s_mask[d * W + x] * pv[x];
-            out[(int64_t)d * L + m] = dsum;  // cumulative over the launch's probes 0..i
+            out[(int64_t)d * n_om + r] = dsum;  // cumulative over the launch's probes 0..i
           }
         }
       }
@@ -458,8 +460,11 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
 #pragma unroll
     for (int t = 0; t < N1; ++t) {
       const int m = (G == 1) ? (j + N2 * (t / N2)) + N1 * (t % N2) : k1g + N1 * (G * t + gg);
-      double* sp = a.S + (int64_t)m * n_k + k;
-      *sp += acc[t];
+      const int row = (m + a.roi_half) & (L - 1);  // rows >= n_om lie outside the energy window
+      if (row < a.n_om) {
+        double* sp = a.S + (int64_t)row * n_k + k;
+        *sp += acc[t];
+      }
     }
   }
 }

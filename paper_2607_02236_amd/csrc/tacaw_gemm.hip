@@ -1,8 +1,9 @@
 // Chunk transform as a dense GEMM on MFMA with split-precision operands.
 //
 // X(m, k) = sum_t F(m, t) y(t, k),  F(m, t) = w(t) exp(-2 pi i m t / L), written as a
-// real GEMM with M = 2L rows (re/im of each bin interleaved), K = 2L (re/im of
-// each frame interleaved) and N = pixels:
+// real GEMM with M = 2 n_om rows (re/im of each output bin interleaved; n_om = L,
+// or the 2M + 1 bins of an energy window, whose other rows are never computed),
+// K = 2L (re/im of each frame interleaved) and N = pixels:
 //   [Xr]   [ Fr  -Fi ] [yr]
 //   [Xi] = [ Fi   Fr ] [yi]
 // Both operands are split into a high and a low half-precision part
@@ -12,7 +13,7 @@
 // scale s per (probe, pixel) that keeps the fp16 low parts in the normal range
 // (s = 1 for bf16). The power is divided by s^2 before accumulation.
 //
-// Workgroup: 8 waves, a tile of 32 pixels (the MFMA N dimension) and all 2L
+// Workgroup: 8 waves, a tile of 32 pixels (the MFMA N dimension) and all
 // rows; wave w owns row blocks {w, w + 8, ...} of 32 rows. Frames are staged
 // through LDS in chunks of KC frames, already converted to the operand order.
 #include "tacaw_internal.h"
@@ -60,16 +61,17 @@ __device__ __forceinline__ f32x16 mfma(h8 a, h8 b, f32x16 c) {
   }
 }
 
-// fmat layout: [2][2L rows][2L] 16-bit (hi then lo), row 2m + c (c = 0 real, 1 imag),
+// fmat layout: [2][m_rows][2L] 16-bit (hi then lo), row 2r + c (c = 0 real, 1 imag) of
+// output row r (bin (r - roi_half) mod L), zero rows up to m_rows (a multiple of 32);
 // column 2t + c' (c' = 0 multiplies Re y, 1 multiplies Im y).
 // gscale: [n_probe][n_k] float, the power-of-two scale s of y.
 template <int L, typename InT, int PREC, bool DP>
 __global__ void __launch_bounds__(64 * kGemmWaves)
-    seg_gemm_kernel(const SegArgs a, const unsigned short* __restrict__ fmat,
+    seg_gemm_kernel(const SegArgs a, const unsigned short* __restrict__ fmat, int m_rows,
                     const float* __restrict__ gscale) {
   constexpr int NT = 64 * kGemmWaves;
-  constexpr int MB = L / 16;            // row blocks of 32 rows (2L rows)
-  constexpr int MBW = MB / kGemmWaves;  // row blocks per wave
+  constexpr int MB = L / 16;            // row blocks of 32 rows at most (2L rows)
+  constexpr int MBW = MB / kGemmWaves;  // row blocks per wave at most
   constexpr int KC = L < kGemmKC ? L : kGemmKC;
   constexpr int KSTEPS = KC / 8;        // 16 real K (8 frames) per MFMA
   constexpr int K2 = 2 * L;
@@ -90,6 +92,8 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
   const int half = lane >> 5;
   const int64_t kcol = (int64_t)tile * kGemmPx + col;
   const bool cvalid = kcol < n_k;
+  const int n_blocks = m_rows / 32;  // row blocks of this plan (energy window)
+  const int n_om = a.n_om;
 
   if constexpr (DP) {
     for (int i = tid; i < kMaxDet * kGemmPx; i += NT) {
@@ -163,12 +167,15 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
           const int kcol2 = 2 * c0 + 16 * kst + 8 * half;  // first of the lane's 8 K columns
 #pragma unroll
           for (int b = 0; b < MBW; ++b) {
-            const int row = 32 * (wave + kGemmWaves * b) + col;
-            const h8 ah = *reinterpret_cast<const h8*>(fmat + (int64_t)row * K2 + kcol2);
-            const h8 al = *reinterpret_cast<const h8*>(fmat + (int64_t)(K2 + row) * K2 + kcol2);
-            acc[b] = mfma<PREC>(ah, bh, acc[b]);
-            acc[b] = mfma<PREC>(ah, bl, acc[b]);
-            acc[b] = mfma<PREC>(al, bh, acc[b]);
+            if (wave + kGemmWaves * b < n_blocks) {  // uniform per wave
+              const int row = 32 * (wave + kGemmWaves * b) + col;
+              const h8 ah = *reinterpret_cast<const h8*>(fmat + (int64_t)row * K2 + kcol2);
+              const h8 al =
+                  *reinterpret_cast<const h8*>(fmat + (int64_t)(m_rows + row) * K2 + kcol2);
+              acc[b] = mfma<PREC>(ah, bh, acc[b]);
+              acc[b] = mfma<PREC>(ah, bl, acc[b]);
+              acc[b] = mfma<PREC>(al, bh, acc[b]);
+            }
           }
         }
       }
@@ -176,20 +183,23 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
       // its 32-row block, column col; rows (2m', 2m'+1) are (Re, Im) of one bin
 #pragma unroll
       for (int b = 0; b < MBW; ++b) {
+        if (wave + kGemmWaves * b < n_blocks) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int v = 4 * (q / 2) + 2 * (q % 2);
-          const float pw = acc[b][v] * acc[b][v] + acc[b][v + 1] * acc[b][v + 1];
-          acc64[b][q] += (double)(pw * inv2);
+          for (int q = 0; q < 8; ++q) {
+            const int v = 4 * (q / 2) + 2 * (q % 2);
+            const float pw = acc[b][v] * acc[b][v] + acc[b][v + 1] * acc[b][v + 1];
+            acc64[b][q] += (double)(pw * inv2);
+          }
         }
       }
     }
 
     if constexpr (DP) {
-      // cumulative detector partials through LDS, two halves of the bins
+      // cumulative detector partials through LDS, two halves of the rows
       double* sd = reinterpret_cast<double*>(bst);  // needs L/2 * 32 doubles
       static_assert(sizeof(bst) >= (size_t)L / 2 * kGemmPx * 8, "LDS for partials");
       const int slot = a.tile_slot[tile];
+      const int hrows = (n_om + 1) / 2;  // <= L/2
       for (int hb = 0; hb < 2; ++hb) {
         __syncthreads();
 #pragma unroll
@@ -197,19 +207,21 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
             const int rblk = wave + kGemmWaves * b;
-            const int m = 16 * rblk + 4 * (q / 2) + 2 * half + (q % 2);
-            if ((m >= L / 2) == (hb == 1)) sd[(m - hb * (L / 2)) * kGemmPx + col] = acc64[b][q];
+            const int r = 16 * rblk + 4 * (q / 2) + 2 * half + (q % 2);
+            if (r < n_om && (r >= hrows) == (hb == 1))
+              sd[(r - hb * hrows) * kGemmPx + col] = acc64[b][q];
           }
         }
         __syncthreads();
         if (slot >= 0) {
-          double* out = a.dpart + ((int64_t)slot * a.n_probes + i) * a.n_det * L;
-          for (int mm = tid; mm < L / 2; mm += NT) {
+          double* out = a.dpart + ((int64_t)slot * a.n_probes + i) * a.n_det * n_om;
+          const int r0 = hb * hrows, nr = hb ? n_om - hrows : hrows;
+          for (int rr = tid; rr < nr; rr += NT) {
             for (int d = 0; d < a.n_det; ++d) {
               double dsum = 0.0;
 #pragma unroll
-              for (int x = 0; x < kGemmPx; ++x) dsum += s_mask[d * kGemmPx + x] * sd[mm * kGemmPx + x];
-              out[(int64_t)d * L + hb * (L / 2) + mm] = dsum;  // cumulative over probes 0..i
+              for (int x = 0; x < kGemmPx; ++x) dsum += s_mask[d * kGemmPx + x] * sd[rr * kGemmPx + x];
+              out[(int64_t)d * n_om + r0 + rr] = dsum;  // cumulative over probes 0..i
             }
           }
         }
@@ -223,45 +235,47 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int rblk = wave + kGemmWaves * b;
-        const int m = 16 * rblk + 4 * (q / 2) + 2 * half + (q % 2);
-        a.S[(int64_t)m * n_k + kcol] += acc64[b][q];
+        const int r = 16 * rblk + 4 * (q / 2) + 2 * half + (q % 2);
+        if (r < n_om) a.S[(int64_t)r * n_k + kcol] += acc64[b][q];
       }
     }
   }
 }
 
 template <int L, typename InT, int PREC>
-static hipError_t launch_g3(const SegArgs& a, const void* fmat, const float* gscale, int n_tiles,
-                            hipStream_t st) {
+static hipError_t launch_g3(const SegArgs& a, const void* fmat, int m_rows, const float* gscale,
+                            int n_tiles, hipStream_t st) {
   if (a.n_det > 0)
     hipLaunchKernelGGL((seg_gemm_kernel<L, InT, PREC, true>), dim3(n_tiles), dim3(64 * kGemmWaves),
-                       0, st, a, (const unsigned short*)fmat, gscale);
+                       0, st, a, (const unsigned short*)fmat, m_rows, gscale);
   else
     hipLaunchKernelGGL((seg_gemm_kernel<L, InT, PREC, false>), dim3(n_tiles), dim3(64 * kGemmWaves),
-                       0, st, a, (const unsigned short*)fmat, gscale);
+                       0, st, a, (const unsigned short*)fmat, m_rows, gscale);
   return hipGetLastError();
 }
 
 template <int L>
 static hipError_t launch_g2(int in_dtype, int prec, const SegArgs& a, const void* fmat,
-                            const float* gscale, int n_tiles, hipStream_t st) {
+                            int m_rows, const float* gscale, int n_tiles, hipStream_t st) {
+  if (m_rows < 32 || m_rows % 32 != 0 || m_rows > 2 * L || m_rows < 2 * a.n_om)
+    return hipErrorInvalidValue;
   if (in_dtype == 1)
-    return prec ? launch_g3<L, double2, 1>(a, fmat, gscale, n_tiles, st)
-                : launch_g3<L, double2, 0>(a, fmat, gscale, n_tiles, st);
-  return prec ? launch_g3<L, float2, 1>(a, fmat, gscale, n_tiles, st)
-              : launch_g3<L, float2, 0>(a, fmat, gscale, n_tiles, st);
+    return prec ? launch_g3<L, double2, 1>(a, fmat, m_rows, gscale, n_tiles, st)
+                : launch_g3<L, double2, 0>(a, fmat, m_rows, gscale, n_tiles, st);
+  return prec ? launch_g3<L, float2, 1>(a, fmat, m_rows, gscale, n_tiles, st)
+              : launch_g3<L, float2, 0>(a, fmat, m_rows, gscale, n_tiles, st);
 }
 
 bool seg_gemm_supported(int L) { return L == 128 || L == 256 || L == 512; }
 int seg_gemm_tile_pixels(int) { return kGemmPx; }
 
 hipError_t launch_seg_gemm(int L, int in_dtype, bool /*sub64*/, int prec, const SegArgs& a,
-                           const void* fmat, int n_tiles, hipStream_t st) {
+                           const void* fmat, int m_rows, int n_tiles, hipStream_t st) {
   const float* gscale = a.gscale;
   switch (L) {
-    case 128: return launch_g2<128>(in_dtype, prec, a, fmat, gscale, n_tiles, st);
-    case 256: return launch_g2<256>(in_dtype, prec, a, fmat, gscale, n_tiles, st);
-    case 512: return launch_g2<512>(in_dtype, prec, a, fmat, gscale, n_tiles, st);
+    case 128: return launch_g2<128>(in_dtype, prec, a, fmat, m_rows, gscale, n_tiles, st);
+    case 256: return launch_g2<256>(in_dtype, prec, a, fmat, m_rows, gscale, n_tiles, st);
+    case 512: return launch_g2<512>(in_dtype, prec, a, fmat, m_rows, gscale, n_tiles, st);
   }
   return hipErrorInvalidValue;
 }

@@ -30,11 +30,13 @@ struct SegArgs {
   const double2* cref;     // [n_probe][n_k] reference subtracted before the window
   double2* msum;           // [n_probe][n_k] FP64 sum of (psi - c) over counted frames
   double2* xs;             // [n_probe][kMaxCorr][n_k] FP64 sum over chunks of X'(bin)
-  double* S;               // [L][n_k] FP64 accumulator of sum |X'|^2
+  double* S;               // [n_om][n_k] FP64 accumulator of sum |X'|^2
+  int32_t n_om;            // output rows: L, or 2 roi_half + 1
+  int32_t roi_half;        // energy window M (0 = all bins); bin m -> row (m + M) mod L
   int32_t n_det;           // per-probe detector partials (0 = off)
   const double* masks;     // [n_det][n_k]
   const int32_t* tile_slot;// [n_tiles] slot in dpart, -1 if no mask touches the tile
-  double* dpart;           // [n_active][n_probes][n_det][L]
+  double* dpart;           // [n_active][n_probes][n_det][n_om]
   const float* gscale;     // GEMM form: [n_probe][n_k] power-of-two scale of psi - mu
 };
 
@@ -45,8 +47,10 @@ int seg_fft_tile_pixels(int L);
 void seg_fft_split(int L, int* n1, int* n2);  // L = N1 * N2 of the push kernel's tables
 bool seg_fft_supported(int L);
 
+// fmat: [2][m_rows][2L] hi and lo parts of the window-folded DFT rows of the
+// output bins (row 2r + c), m_rows = 2 n_om rounded up to a multiple of 32
 hipError_t launch_seg_gemm(int L, int in_dtype, bool sub64, int prec, const SegArgs& a,
-                           const void* fmat, int n_tiles, hipStream_t st);
+                           const void* fmat, int m_rows, int n_tiles, hipStream_t st);
 int seg_gemm_tile_pixels(int L);
 bool seg_gemm_supported(int L);
 hipError_t launch_gemm_scale(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
@@ -69,8 +73,8 @@ hipError_t launch_dpart_reduce(const double* dpart, int32_t n_active, int32_t n_
                                double* Dp, hipStream_t st);
 
 struct CorrArgs {
-  int32_t n_k, n_probe, L, n_corr, mean_global;
-  int32_t bins[kMaxCorr];
+  int32_t n_k, n_probe, n_om, n_corr, mean_global;
+  int32_t rows[kMaxCorr];  // output rows of the correction bins
   double2 wbin[kMaxCorr];  // W(bin) = sum_t w(t) exp(-2 pi i bin t / L)
   double inv_nused;        // 1 / frames_used
   double n_seg;            // N_s
@@ -78,9 +82,9 @@ struct CorrArgs {
   const double2* msum;
   const double2* xs;
 };
-// S[i] <- kappa * q[(i / inner) % L] * S[i] (q may be null), copied to out when given
+// S[i] <- kappa * q[(i / inner) % n_om] * S[i] (q may be null), copied to out when given
 hipError_t launch_finalize_S(double* S, double* out, int64_t n_elem, double kappa, const double* q,
-                             int64_t inner, int32_t L, hipStream_t st);
+                             int64_t inner, int32_t n_om, hipStream_t st);
 hipError_t launch_correct_S(const CorrArgs& c, double* S, double* out, double kappa, hipStream_t st);
 hipError_t launch_correct_Dp(const CorrArgs& c, const double* masks, int32_t n_det, double* Dp,
                              hipStream_t st);
@@ -94,6 +98,7 @@ struct BwdArgs {
   int64_t pstride, fstride;
   void* grad;              // same layout as in
   int32_t n_k, probe0, n_probes, n_probe_total, n_seg, hop, n_det;
+  int32_t n_om, roi_half;  // output rows and energy window (bin m -> row (m + M) mod L)
   int32_t mean_global;
   double inv_nused;
   int64_t n_used;
@@ -102,12 +107,12 @@ struct BwdArgs {
   const float2* tw;        // [N2][N1]
   const double2* cref;     // reference (first frame or exact mean)
   const double2* mu;       // [n_probe][n_k] exact mean (GLOBAL) for the adjoint
-  const double* gS;        // [L][n_k] or null
-  const double* gD;        // [n_det][L] or null
-  const double* gDp;       // [n_det][n_probe][L] or null
+  const double* gS;        // [n_om][n_k] or null
+  const double* gD;        // [n_det][n_om] or null
+  const double* gDp;       // [n_det][n_probe][n_om] or null
   const double* masks;     // [n_det][n_k]
   double kappa_S, kappa_p; // normalisations of S and S_p
-  const double* qfac;      // [L] quantum-statistics factor or null
+  const double* qfac;      // [n_om] quantum-statistics factor per row, or null
   double2* gmean;          // [n_probes][n_k] sum over chunks and t of w * grad_y (mean term)
   double* dwpart;          // [n_tiles][2] partial sums: r-derivative term, loss value
 };

@@ -112,12 +112,15 @@ float f16_value(uint16_t b) {
 }
 
 // Window-folded DFT matrix of the GEMM form as hi and lo 16-bit parts:
-// [2][2L][2L], row 2m + c (c: 0 real, 1 imaginary part of bin m), column 2t + c'
-// (c' multiplies Re or Im of frame t): [[Fr, -Fi], [Fi, Fr]] interleaved.
-std::vector<uint16_t> make_dft_matrix(const std::vector<double>& w, bool fp16) {
+// [2][m_rows][2L], row 2r + c (c: 0 real, 1 imaginary part of output row r, which
+// holds bin m = (r - roi_half) mod L), column 2t + c' (c' multiplies Re or Im of
+// frame t): [[Fr, -Fi], [Fi, Fr]] interleaved; rows from 2 n_om on are zero.
+std::vector<uint16_t> make_dft_matrix(const std::vector<double>& w, bool fp16, int n_om,
+                                      int roi_half, int m_rows) {
   const int L = (int)w.size(), K2 = 2 * L;
-  std::vector<uint16_t> out((size_t)2 * K2 * K2);
-  for (int m = 0; m < L; ++m) {
+  std::vector<uint16_t> out((size_t)2 * m_rows * K2, 0);
+  for (int r = 0; r < n_om; ++r) {
+    const int m = (r - roi_half + L) % L;
     for (int t = 0; t < L; ++t) {
       const double ang = -6.283185307179586476925286766559 * (double)(((int64_t)m * t) % L) / L;
       const double fr = w[t] * std::cos(ang), fi = w[t] * std::sin(ang);
@@ -134,9 +137,9 @@ std::vector<uint16_t> make_dft_matrix(const std::vector<double>& w, bool fp16) {
             hi = bf16_bits(vf);
             lo = bf16_bits((float)(v - (double)bf16_value(hi)));
           }
-          const size_t idx = (size_t)(2 * m + c) * K2 + (2 * t + cp);
+          const size_t idx = (size_t)(2 * r + c) * K2 + (2 * t + cp);
           out[idx] = hi;
-          out[(size_t)K2 * K2 + idx] = lo;
+          out[(size_t)m_rows * K2 + idx] = lo;
         }
       }
     }
@@ -151,10 +154,12 @@ struct tacaw_plan_s {
   hipStream_t st = nullptr;
   int device = 0;
   int L = 0, H = 0, Ns = 0, n_k = 0, N1 = 0, N2 = 0, W = 0, n_tiles = 0;
+  int n_om = 0, roi = 0, m_rows = 0;  // output rows, energy window M, GEMM rows
   int64_t n_used = 0;
   double sumw2 = 0.0;
   int n_corr = 0;
-  int bins[kMaxCorr] = {0, 0, 0};
+  int bins[kMaxCorr] = {0, 0, 0};  // correction bins 0, 1, L-1 and their output rows
+  int rows[kMaxCorr] = {0, 0, 0};
   double2 wbin[kMaxCorr];
   bool compact = false;
   int strategy = kRefFirstFrame;
@@ -174,10 +179,10 @@ struct tacaw_plan_s {
   double2* cref = nullptr;  // [P][n_k]
   double2* msum = nullptr;  // [P][n_k]
   double2* xs = nullptr;    // [P][3][n_k]
-  double* S = nullptr;      // [L][n_k]
+  double* S = nullptr;      // [n_om][n_k]
   double* masks = nullptr;  // [n_det][n_k]
   int32_t* tile_slot = nullptr;
-  double* Dp = nullptr;     // [n_det][P][L]
+  double* Dp = nullptr;     // [n_det][P][n_om]
   double* dpart = nullptr;
   int64_t dpart_bytes = 0;
   void* ring = nullptr;
@@ -186,7 +191,7 @@ struct tacaw_plan_s {
   double* scratch = nullptr;
   int64_t scratch_bytes = 0;
   float* gscale = nullptr;  // GEMM form: [P][n_k]
-  double* qfac = nullptr;   // [L] quantum-statistics factor per bin (temperature > 0)
+  double* qfac = nullptr;   // [n_om] quantum-statistics factor per row (temperature > 0)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
 
@@ -286,8 +291,11 @@ int tacaw_plan_check(const tacaw_plan_desc* d) {
   if (d->n_det > 0 && !d->d_masks) return fail(TACAW_ERR_INVALID_ARG, "n_det > 0 needs d_masks");
   if (d->max_probes_in_flight < 0 || d->max_probes_in_flight > d->n_probe)
     return fail(TACAW_ERR_INVALID_ARG, "max_probes_in_flight must be in [0, n_probe]");
+  if (d->omega_half < 0 || d->omega_half > d->seg_len / 2 - 1)
+    return fail(TACAW_ERR_INVALID_ARG, "omega_half must be in [0, seg_len/2 - 1]");
   const int64_t n_k = (int64_t)d->ny * d->nx;
-  const int64_t need = (int64_t)d->seg_len * n_k * 8 + (int64_t)d->n_probe * n_k * 80 +
+  const int64_t n_om = d->omega_half > 0 ? 2 * (int64_t)d->omega_half + 1 : d->seg_len;
+  const int64_t need = n_om * n_k * 8 + (int64_t)d->n_probe * n_k * 80 +
                        (int64_t)d->n_det * n_k * 8;
   if (need > kMaxDeviceBytes) return fail(TACAW_ERR_OOM, "plan accumulators exceed device memory");
   return TACAW_OK;
@@ -307,6 +315,9 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   P->n_used = (int64_t)(P->Ns - 1) * P->H + P->L;
   P->n_k = d->ny * d->nx;
   P->esz = d->in_dtype == TACAW_C128 ? 16 : 8;
+  P->roi = d->omega_half;
+  P->n_om = P->roi > 0 ? 2 * P->roi + 1 : P->L;
+  P->m_rows = (2 * P->n_om + 31) / 32 * 32;
   const bool gemm = transform_is_gemm(d->transform);
   P->W = gemm ? seg_gemm_tile_pixels(P->L) : seg_fft_tile_pixels(P->L);
   P->n_tiles = (P->n_k + P->W - 1) / P->W;
@@ -348,6 +359,7 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   P->bins[0] = 0;
   P->bins[1] = 1;
   P->bins[2] = P->L - 1;
+  for (int b = 0; b < kMaxCorr; ++b) P->rows[b] = (P->bins[b] + P->roi) % P->L;
   for (int b = 0; b < kMaxCorr; ++b) P->wbin[b] = Wm[P->bins[b]];
   if (gemm)  // the GEMM form subtracts the exact mean (or zero) before splitting
     P->strategy = d->mean_mode == TACAW_MEAN_GLOBAL ? kRefExactMean : kRefZero;
@@ -390,17 +402,17 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   A((void**)&P->cref, np * nk * 16, "references");
   A((void**)&P->msum, np * nk * 16, "mean sums");
   A((void**)&P->xs, np * kMaxCorr * nk * 16, "correction sums");
-  A((void**)&P->S, (int64_t)P->L * nk * 8, "spectrum accumulator");
+  A((void**)&P->S, (int64_t)P->n_om * nk * 8, "spectrum accumulator");
   A((void**)&P->scratch, 64, "scratch");
-  if (d->temperature_K > 0.0) A((void**)&P->qfac, (int64_t)P->L * 8, "quantum factor");
+  if (d->temperature_K > 0.0) A((void**)&P->qfac, (int64_t)P->n_om * 8, "quantum factor");
   if (gemm) {
-    A(&P->fmat, (int64_t)2 * (2 * P->L) * (2 * P->L) * 2, "DFT matrix");
+    A(&P->fmat, (int64_t)2 * P->m_rows * (2 * P->L) * 2, "DFT matrix");
     A((void**)&P->gscale, np * nk * 4, "operand scales");
   }
   if (d->n_det > 0) {
     A((void**)&P->masks, (int64_t)d->n_det * nk * 8, "masks");
     A((void**)&P->tile_slot, (int64_t)P->n_tiles * 4, "tile slots");
-    A((void**)&P->Dp, (int64_t)d->n_det * np * P->L * 8, "per-probe detector spectra");
+    A((void**)&P->Dp, (int64_t)d->n_det * np * P->n_om * 8, "per-probe detector spectra");
   }
   if (rc != TACAW_OK) {
     delete P;
@@ -416,17 +428,19 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
     // E_m = h nu_m, nu_m = m / (L dt) (m < L/2) or (m - L) / (L dt); factor x / (1 - e^-x),
     // x = E_m / (k_B T), limit 1 at E = 0
     const double h_ev_s = 6.62607015e-34 / 1.602176634e-19, kb_ev_k = 8.617333262e-5;
-    std::vector<double> q(P->L);
-    for (int m = 0; m < P->L; ++m) {
+    std::vector<double> q(P->n_om);
+    for (int r = 0; r < P->n_om; ++r) {
+      const int m = (r - P->roi + P->L) % P->L;
       const int sm = m < (P->L + 1) / 2 ? m : m - P->L;
       const double e = h_ev_s * (double)sm / ((double)P->L * d->dt_fs * 1e-15);
       const double x = e / (kb_ev_k * d->temperature_K);
-      q[m] = x == 0.0 ? 1.0 : x / (-std::expm1(-x));
+      q[r] = x == 0.0 ? 1.0 : x / (-std::expm1(-x));
     }
-    H2D(P->qfac, q.data(), (int64_t)P->L * 8);
+    H2D(P->qfac, q.data(), (int64_t)P->n_om * 8);
   }
   if (gemm && rc == TACAW_OK) {
-    const std::vector<uint16_t> fm = make_dft_matrix(w, d->transform == TACAW_GEMM_F16X3);
+    const std::vector<uint16_t> fm =
+        make_dft_matrix(w, d->transform == TACAW_GEMM_F16X3, P->n_om, P->roi, P->m_rows);
     H2D(P->fmat, fm.data(), (int64_t)fm.size() * 2);
   }
   if (d->n_det > 0 && rc == TACAW_OK) {
@@ -474,9 +488,9 @@ int tacaw_reset(tacaw_plan_t P) {
   TRY(hip_check(launch_fill_zero(P->cref, np * nk * 16, P->st), "reset"));
   TRY(hip_check(launch_fill_zero(P->msum, np * nk * 16, P->st), "reset"));
   TRY(hip_check(launch_fill_zero(P->xs, np * kMaxCorr * nk * 16, P->st), "reset"));
-  TRY(hip_check(launch_fill_zero(P->S, (int64_t)P->L * nk * 8, P->st), "reset"));
+  TRY(hip_check(launch_fill_zero(P->S, (int64_t)P->n_om * nk * 8, P->st), "reset"));
   if (P->Dp)
-    TRY(hip_check(launch_fill_zero(P->Dp, (int64_t)P->d.n_det * np * P->L * 8, P->st), "reset"));
+    TRY(hip_check(launch_fill_zero(P->Dp, (int64_t)P->d.n_det * np * P->n_om * 8, P->st), "reset"));
   std::fill(P->cursor.begin(), P->cursor.end(), 0);
   std::fill(P->slot_owner.begin(), P->slot_owner.end(), -1);
   P->state = 0;
@@ -494,7 +508,7 @@ int tacaw_plan_get_info(tacaw_plan_t P, tacaw_plan_info* info) {
   if (!P || !info) return fail(TACAW_ERR_INVALID_ARG, "plan or info is NULL");
   std::memset(info, 0, sizeof(*info));
   info->n_segments = P->Ns;
-  info->n_omega = P->L;
+  info->n_omega = P->n_om;
   info->frames_used = P->n_used;
   info->frames_dropped = P->dropped;
   info->device_bytes = P->bytes;
@@ -566,7 +580,7 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
   }
   int64_t dpart_need = 0;
   if (P->d.n_det > 0 && s_hi > s_lo)
-    dpart_need = (int64_t)std::max(P->n_active, 1) * n_probes * P->d.n_det * P->L * 8;
+    dpart_need = (int64_t)std::max(P->n_active, 1) * n_probes * P->d.n_det * P->n_om * 8;
   if (dpart_need > P->dpart_bytes) {
     P->release((void**)&P->dpart);
     P->dpart_bytes = 0;
@@ -613,6 +627,8 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
     g.msum = P->msum;
     g.xs = P->xs;
     g.S = P->S;
+    g.n_om = P->n_om;
+    g.roi_half = P->roi;
     g.n_det = P->d.n_det;
     g.masks = P->masks;
     g.tile_slot = P->tile_slot;
@@ -623,7 +639,7 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
     if (transform_is_gemm(P->d.transform))
       TRY(hip_check(launch_seg_gemm(P->L, P->d.in_dtype, sub64,
                                     P->d.transform == TACAW_GEMM_F16X3 ? 1 : 0, g, P->fmat,
-                                    P->n_tiles, P->st),
+                                    P->m_rows, P->n_tiles, P->st),
                     "chunk GEMM kernel"));
     else
       TRY(hip_check(launch_seg_fft(P->L, P->d.in_dtype, sub64, g, P->n_tiles, P->st),
@@ -633,7 +649,7 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
       P->timed = true;
     }
     if (P->d.n_det > 0 && P->n_active > 0)
-      TRY(hip_check(launch_dpart_reduce(P->dpart, P->n_active, n_probes, P->d.n_det, P->L, probe0,
+      TRY(hip_check(launch_dpart_reduce(P->dpart, P->n_active, n_probes, P->d.n_det, P->n_om, probe0,
                                         P->d.n_probe, P->Dp, P->st),
                     "detector partial reduce"));
   }
@@ -660,11 +676,11 @@ static CorrArgs corr_args(tacaw_plan_t P) {
   CorrArgs c{};
   c.n_k = P->n_k;
   c.n_probe = P->d.n_probe;
-  c.L = P->L;
+  c.n_om = P->n_om;
   c.n_corr = P->n_corr;
   c.mean_global = P->d.mean_mode == TACAW_MEAN_GLOBAL ? 1 : 0;
   for (int b = 0; b < kMaxCorr; ++b) {
-    c.bins[b] = P->bins[b];
+    c.rows[b] = P->rows[b];
     c.wbin[b] = P->wbin[b];
   }
   c.inv_nused = 1.0 / (double)P->n_used;
@@ -693,12 +709,12 @@ int tacaw_finalize(tacaw_plan_t P, double* d_S) {
     if (P->d.n_det > 0)
       TRY(hip_check(launch_correct_Dp(c, P->masks, P->d.n_det, P->Dp, P->st), "mean correction"));
   }
-  TRY(hip_check(launch_finalize_S(P->S, d_S, (int64_t)P->L * P->n_k, kappa_S(P), P->qfac,
-                                  P->n_k, P->L, P->st),
+  TRY(hip_check(launch_finalize_S(P->S, d_S, (int64_t)P->n_om * P->n_k, kappa_S(P), P->qfac,
+                                  P->n_k, P->n_om, P->st),
                 "normalisation"));
   if (P->d.n_det > 0)
-    TRY(hip_check(launch_finalize_S(P->Dp, nullptr, (int64_t)P->d.n_det * P->d.n_probe * P->L,
-                                    kappa_probe(P), P->qfac, 1, P->L, P->st),
+    TRY(hip_check(launch_finalize_S(P->Dp, nullptr, (int64_t)P->d.n_det * P->d.n_probe * P->n_om,
+                                    kappa_probe(P), P->qfac, 1, P->n_om, P->st),
                   "normalisation"));
   P->state = 1;
   return TACAW_OK;
@@ -718,11 +734,11 @@ int tacaw_detector_spectra(tacaw_plan_t P, const double* d_masks, int32_t n_det,
     return fail(TACAW_ERR_INVALID_ARG, "per-probe spectra need the plan's own masks");
   if (n_det > 0 && !d_D && !d_Dp) return fail(TACAW_ERR_INVALID_ARG, "no output");
   if (n_det > 0 && d_D) {
-    TRY(hip_check(launch_fill_zero(d_D, (int64_t)n_det * P->L * 8, P->st), "zero D"));
-    TRY(hip_check(launch_detector(P->S, masks, n_det, P->L, P->n_k, d_D, P->st), "detector"));
+    TRY(hip_check(launch_fill_zero(d_D, (int64_t)n_det * P->n_om * 8, P->st), "zero D"));
+    TRY(hip_check(launch_detector(P->S, masks, n_det, P->n_om, P->n_k, d_D, P->st), "detector"));
   }
   if (d_Dp)
-    TRY(hip_check(hipMemcpyAsync(d_Dp, P->Dp, (size_t)P->d.n_det * P->d.n_probe * P->L * 8,
+    TRY(hip_check(hipMemcpyAsync(d_Dp, P->Dp, (size_t)P->d.n_det * P->d.n_probe * P->n_om * 8,
                                  hipMemcpyDeviceToDevice, P->st),
                   "per-probe copy"));
   return TACAW_OK;
@@ -776,6 +792,8 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   b.n_seg = P->Ns;
   b.hop = P->H;
   b.n_det = P->d.n_det;
+  b.n_om = P->n_om;
+  b.roi_half = P->roi;
   b.mean_global = global ? 1 : 0;
   b.inv_nused = 1.0 / (double)P->n_used;
   b.n_used = P->n_used;

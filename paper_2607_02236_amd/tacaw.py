@@ -42,6 +42,7 @@ class PlanDesc(C.Structure):
         ("n_det", C.c_int32), ("d_masks", C.c_void_p),
         ("max_probes_in_flight", C.c_int32), ("flags", C.c_int32),
         ("temperature_K", C.c_double), ("h_window", C.c_void_p),
+        ("omega_half", C.c_int32),
     ]
 
 
@@ -95,8 +96,10 @@ def _check(rc):
 def make_desc(n_probe, ny, nx, n_frames, seg_len, hop, window="hann", window_param=1.0,
               mean_mode="global", transform="fft", in_dtype="c64", probe_reduce="mean",
               dt_fs=5.0, n_det=0, masks_ptr=0, max_probes_in_flight=0, flags=0,
-              temperature_K=0.0, window_values=None) -> PlanDesc:
-    """window may be a name or an array of seg_len values (custom window)."""
+              temperature_K=0.0, window_values=None, omega_half=0) -> PlanDesc:
+    """window may be a name or an array of seg_len values (custom window).
+    omega_half = M > 0 keeps only the 2M + 1 bins of signed index -M..M
+    (ascending); axes.omega_half_for converts a frequency or energy limit."""
     wptr = None
     if not isinstance(window, str):
         import numpy as np
@@ -109,7 +112,8 @@ def make_desc(n_probe, ny, nx, n_frames, seg_len, hop, window="hann", window_par
                  WINDOWS[window], float(window_param), MEANS[mean_mode],
                  TRANSFORMS[transform], DTYPES[in_dtype], REDUCE[probe_reduce],
                  float(dt_fs), int(n_det), C.c_void_p(masks_ptr or None),
-                 int(max_probes_in_flight), int(flags), float(temperature_K), C.c_void_p(wptr))
+                 int(max_probes_in_flight), int(flags), float(temperature_K), C.c_void_p(wptr),
+                 int(omega_half))
     d._window_values = window_values  # keep the host array alive with the descriptor
     return d
 
@@ -136,7 +140,7 @@ class Plan:
     def __init__(self, n_probe, ny, nx, n_frames, seg_len, hop=None, window="hann",
                  window_param=1.0, mean_mode="global", transform="fft", in_dtype="c64",
                  probe_reduce="mean", dt_fs=5.0, masks=None, max_probes_in_flight=0,
-                 stream=None, time_kernels=False, temperature_K=0.0):
+                 stream=None, time_kernels=False, temperature_K=0.0, omega_half=0):
         self.handle = None
         hop = seg_len // 2 if hop is None else hop
         self.n_probe, self.ny, self.nx = int(n_probe), int(ny), int(nx)
@@ -157,11 +161,13 @@ class Plan:
         self.stream, sptr = _stream_ptr(stream)
         self.desc = make_desc(n_probe, ny, nx, n_frames, seg_len, hop, window, window_param,
                               mean_mode, transform, in_dtype, probe_reduce, dt_fs, n_det, mptr,
-                              max_probes_in_flight, 1 if time_kernels else 0, temperature_K)
+                              max_probes_in_flight, 1 if time_kernels else 0, temperature_K,
+                              omega_half=omega_half)
         h = C.c_void_p()
         _check(lib.tacaw_plan(C.byref(self.desc), sptr, C.byref(h)))
         self.handle = h
         self._keep = []
+        self._n_omega = self.info()["n_omega"]
 
     # ------------------------------------------------------------------
     def info(self) -> dict:
@@ -171,7 +177,8 @@ class Plan:
 
     @property
     def n_omega(self):
-        return self.seg_len
+        """Output bins: seg_len, or 2 omega_half + 1 with an energy window."""
+        return self._n_omega
 
     def _frames_args(self, frames):
         if frames.dtype != self.tdtype:
@@ -198,8 +205,8 @@ class Plan:
 
     def finalize(self, out: torch.Tensor | None = None) -> torch.Tensor:
         if out is None:
-            out = torch.empty((self.seg_len, self.ny, self.nx), dtype=torch.float64, device="cuda")
-        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != self.seg_len * self.ny * self.nx:
+            out = torch.empty((self.n_omega, self.ny, self.nx), dtype=torch.float64, device="cuda")
+        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != self.n_omega * self.ny * self.nx:
             raise ValueError("out must be a contiguous float64 [n_omega, ny, nx] tensor")
         _check(lib.tacaw_finalize(self.handle, C.c_void_p(out.data_ptr())))
         return out
@@ -214,10 +221,10 @@ class Plan:
             self._keep = [m]
         else:
             n_det, mptr = self.n_det, C.c_void_p(None)
-        D = out if out is not None else torch.empty((n_det, self.seg_len), dtype=torch.float64, device="cuda")
+        D = out if out is not None else torch.empty((n_det, self.n_omega), dtype=torch.float64, device="cuda")
         Dp = None
         if per_probe:
-            Dp = out_p if out_p is not None else torch.empty((self.n_det, self.n_probe, self.seg_len),
+            Dp = out_p if out_p is not None else torch.empty((self.n_det, self.n_probe, self.n_omega),
                                                              dtype=torch.float64, device="cuda")
         _check(lib.tacaw_detector_spectra(self.handle, mptr, int(n_det), C.c_void_p(D.data_ptr()),
                                           C.c_void_p(Dp.data_ptr() if Dp is not None else None)))

@@ -57,6 +57,8 @@ def _ok(**over):
     (dict(window="custom"), "INVALID_ARG"),
     (dict(temperature_K=-1.0), "INVALID_ARG"),
     (dict(transform="gemm_f16x3", seg_len=1024, n_frames=2048, hop=512), "UNSUPPORTED"),
+    (dict(omega_half=-1), "INVALID_ARG"),
+    (dict(omega_half=64), "INVALID_ARG"),  # must be < seg_len / 2
 ])
 def test_descriptor_validation_errors(over, kind):
     from paper_2607_02236_amd import tacaw
@@ -77,6 +79,8 @@ def test_valid_descriptors_pass():
 
     tacaw.check_desc(**_ok(window=np.hanning(128), temperature_K=300.0))
     tacaw.check_desc(**_ok(transform="gemm_bf16x3"))
+    tacaw.check_desc(**_ok(omega_half=63))
+    tacaw.check_desc(**_ok(omega_half=1, transform="gemm_f16x3", temperature_K=50.0))
 
 
 def test_null_arguments_are_rejected_without_a_device():
@@ -94,9 +98,19 @@ def test_null_arguments_are_rejected_without_a_device():
 
 
 def test_axes_helpers_match_paper_numbers():
+    import numpy as np
+
     from paper_2607_02236_amd import axes
 
     assert len(axes.roi_bins(200, 15.0, 30.0)) == 181
+    # the 181-bin window of +-30 THz at L = 200, 15 fs as a plan's omega_half
+    M = axes.omega_half_for(200, 15.0, f_max_thz=30.0)
+    assert 2 * M + 1 == 181
+    np.testing.assert_array_equal(np.sort(axes.window_rows(200, M)), axes.roi_bins(200, 15.0, 30.0))
+    assert axes.omega_half_for(512, 5.0, e_max_mev=100.0) == 61  # 100 meV / 1.6155 meV
+    assert axes.omega_half_for(256, 5.0, f_max_thz=1e9) == 127
+    np.testing.assert_array_equal(axes.window_rows(8, 0), np.arange(8))
+    np.testing.assert_array_equal(axes.window_rows(8, 2), [6, 7, 0, 1, 2])
     assert round(axes.energy_step_mev(200, 15.0), 1) == 1.4
     e = axes.energy_mev(256, 5.0)
     assert e[1] > 0 and e[255] < 0 and abs(e[128]) == pytest.approx(413.567, rel=1e-5)

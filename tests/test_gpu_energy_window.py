@@ -1,0 +1,147 @@
+"""Energy window (the centred +-ROI of Sec. II.B and App. B): a plan with
+omega_half = M keeps the 2M + 1 bins of signed index -M..M in ascending order.
+
+The FFT form computes every bin and stores the window, so its rows must equal
+the full plan's rows exactly; the DFT-GEMM form computes only the window's rows
+of the DFT matrix. Both, and the adjoint restricted to the window, are checked
+against the FP64 oracle on the same seeded inputs."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import tacaw_synth as T
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def tacaw():
+    from paper_2607_02236_amd import tacaw as t
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def rows_of(L, M):
+    """FFT-order bin of each output row (ascending signed index -M..M)."""
+    return np.mod(np.arange(-M, M + 1), L)
+
+
+def run(tacaw, psi, L, H, masks, **kw):
+    P, NT, ny, nx = psi.shape
+    plan = tacaw.Plan(P, ny, nx, NT, L, H, masks=torch.from_numpy(masks).cuda(), **kw)
+    plan.push(psi.cuda())
+    S = plan.finalize()
+    D, Dp = plan.detector_spectra(per_probe=True)
+    torch.cuda.synchronize()
+    out = {"S": S.cpu().numpy().reshape(plan.n_omega, -1), "D": D.cpu().numpy(),
+           "Dp": Dp.cpu().numpy(), "info": plan.info()}
+    plan.close()
+    return out
+
+
+def oracle_rows(psi, L, H, masks, rows, w=None, q=None):
+    w = O.window("hann", L) if w is None else w
+    S, Sp = O.tacaw_spectra(psi.numpy(), L, H, w)
+    if q is not None:
+        S = S * q[:, None]
+        Sp = Sp * q[None, :, None]
+    S, Sp = S[rows], Sp[:, rows]
+    return {"S": S, "D": O.detector_spectra(S, masks),
+            "Dp": np.transpose(O.detector_spectra(Sp, masks), (1, 0, 2))}
+
+
+def check(g, o, tol, label):
+    eS = rel(g["S"], o["S"])
+    eD = max(rel(g["D"][j], o["D"][j]) for j in range(o["D"].shape[0]))
+    eDp = max(rel(g["Dp"][j], o["Dp"][j]) for j in range(o["D"].shape[0]))
+    print(f"{label}: S {eS:.2e} D {eD:.2e} Dp {eDp:.2e}", flush=True)
+    assert eS <= tol and eD <= tol and eDp <= tol
+
+
+@pytest.mark.parametrize("L,H,NT,ny,nx,P,M", [
+    (512, 256, 1536, 12, 25, 2, 61),   # +-100 meV at 5 fs
+    (128, 64, 640, 37, 29, 3, 1),      # narrowest window: the correction bins only
+    (256, 128, 700, 16, 20, 2, 127),   # widest window: all bins but the Nyquist bin
+    (1024, 512, 2048, 5, 20, 1, 200),
+])
+def test_fft_window_rows_equal_full_plan_and_oracle(tacaw, L, H, NT, ny, nx, P, M):
+    spec = T.SeriesSpec(P, NT, ny, nx, dtype="c64", seed=L + M, model="lines", n_terms=8,
+                        amplitude=1e-3 / np.sqrt(8))
+    psi = T.generate(spec)
+    masks = T.standard_masks(ny, nx, scale=min(ny, nx) / 128)
+    masks[3] = np.random.default_rng(3).random((ny, nx))
+    full = run(tacaw, psi, L, H, masks)
+    win = run(tacaw, psi, L, H, masks, omega_half=M)
+    rows = rows_of(L, M)
+    assert win["info"]["n_omega"] == 2 * M + 1
+    assert np.array_equal(win["S"], full["S"][rows])  # same arithmetic, fewer rows stored
+    assert rel(win["D"], full["D"][:, rows]) <= 1e-12
+    assert rel(win["Dp"], full["Dp"][:, :, rows]) <= 1e-12
+    check(win, oracle_rows(psi, L, H, masks, rows), 1e-5, f"fft L={L} M={M}")
+
+
+@pytest.mark.parametrize("form,tol", [("gemm_f16x3", 1e-5), ("gemm_bf16x3", 1e-4)])
+@pytest.mark.parametrize("L,H,NT,P,M", [
+    (512, 256, 1024, 2, 61),   # 123 rows: 8 row blocks of 32, one per wave
+    (128, 64, 640, 3, 5),      # 11 rows: one row block
+    (256, 256, 768, 2, 127),   # 255 rows
+])
+def test_gemm_computes_only_window_rows(tacaw, form, tol, L, H, NT, P, M):
+    ny, nx = 9, 11
+    spec = T.SeriesSpec(P, NT, ny, nx, dtype="c64", seed=90 + M, model="lines", n_terms=8,
+                        amplitude=1e-3 / np.sqrt(8))
+    psi = T.generate(spec)
+    masks = T.standard_masks(ny, nx, scale=0.08)
+    masks[3] = np.random.default_rng(4).random((ny, nx))
+    g = run(tacaw, psi, L, H, masks, transform=form, omega_half=M)
+    check(g, oracle_rows(psi, L, H, masks, rows_of(L, M)), tol, f"{form} L={L} M={M}")
+
+
+def test_window_with_quantum_factor(tacaw):
+    L, H, dt, T_K, M = 256, 128, 5.0, 300.0, 40
+    spec = T.SeriesSpec(2, 512, 8, 8, dtype="c64", seed=29, model="lines", n_terms=8)
+    psi = T.generate(spec)
+    masks = T.standard_masks(8, 8, scale=0.05)
+    g = run(tacaw, psi, L, H, masks, temperature_K=T_K, dt_fs=dt, omega_half=M)
+    q = O.quantum_factor(O.energy_axis_mev(L, dt), T_K)
+    check(g, oracle_rows(psi, L, H, masks, rows_of(L, M), q=q), 1e-5, "window + quantum factor")
+
+
+def test_adjoint_restricted_to_window(tacaw):
+    from paper_2607_02236_amd import autograd as ag
+
+    L, H, NT, ny, nx, P, M = 256, 128, 600, 9, 13, 2, 30
+    spec = T.SeriesSpec(P, NT, ny, nx, dtype="c64", seed=33, model="lines", n_terms=8)
+    psi = T.generate(spec)
+    masks = T.standard_masks(ny, nx, scale=0.07)
+    n_om = 2 * M + 1
+    a = np.random.default_rng(7).random((4, n_om))
+    b = np.random.default_rng(8).random((4, P, n_om)) * 0.3
+    gS = np.random.default_rng(9).random((n_om, ny * nx)) * 0.1
+    x = psi.cuda().requires_grad_(True)
+    S, D, Dp = ag.spectra(x, L, H, masks=torch.from_numpy(masks), omega_half=M)
+    assert S.shape[0] == n_om and D.shape == (4, n_om)
+    loss = (D * torch.from_numpy(a).cuda()).sum() + (Dp * torch.from_numpy(b).cuda()).sum() \
+        + (S.reshape(n_om, -1) * torch.from_numpy(gS).cuda()).sum()
+    loss.backward()
+    # the same loss on the full spectrum: upstream weights zero outside the window
+    rows = rows_of(L, M)
+    Mf = masks.reshape(4, -1)
+    gS_full = np.zeros((L, ny * nx))
+    gS_full[rows] = gS + np.einsum("jm,jk->mk", a, Mf)
+    gSp_full = np.zeros((P, L, ny * nx))
+    gSp_full[:, rows] = np.einsum("jpm,jk->pmk", b, Mf)
+    g_o, _, lval = O.spectra_vjp(psi.numpy(), L, H, O.window("hann", L), gS_full, gSp_full)
+    assert float(loss) == pytest.approx(lval, rel=1e-5)
+    e = rel(x.grad.cpu().numpy(), g_o)
+    print(f"adjoint in the window M={M}: grad rel err {e:.2e}", flush=True)
+    assert e <= 1e-5
