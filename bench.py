@@ -91,9 +91,13 @@ def main():
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--seg-len", type=int, default=512)
     ap.add_argument("--form", default="fft", choices=["fft", "gemm_bf16x3", "gemm_f16x3"])
-    ap.add_argument("--workload", default="realistic", choices=["realistic", "precision"],
+    ap.add_argument("--workload", default="realistic",
+                    choices=["realistic", "precision", "streaming"],
                     help="realistic: 64 probes x 2048 frames x 256^2 c64 (default); precision: "
-                         "1 probe x 512 frames x 64^2 c128, one chunk of 512")
+                         "1 probe x 512 frames x 64^2 c128, one chunk of 512; streaming: "
+                         "--probes (default 2) x 4096 frames x 1024^2 c64, L=1024 H=512, "
+                         "pushed in pieces of --push-frames frames through the plan's ring")
+    ap.add_argument("--push-frames", type=int, default=256)
     ap.add_argument("--roi-mev", type=float, default=0.0,
                     help="keep only the energy window |E| <= this (0: all bins); the DFT-GEMM "
                          "form then computes only the window's rows")
@@ -118,6 +122,10 @@ def main():
     if args.workload == "precision":
         L, H = 512, 512
         spec = T.config_precision(n_frames=512)
+    elif args.workload == "streaming":
+        L, H = 1024, 512
+        n_pr = args.probes if args.probes != 64 else 2
+        spec = T.config_streaming(n_probe=n_pr, n_frames=4096, ny=1024, nx=1024)
     else:
         L, H = args.seg_len, args.seg_len // 2
         spec = T.config_realistic(n_probe=args.probes, n_frames=args.frames, ny=args.grid,
@@ -142,6 +150,7 @@ def main():
         log(f"copy probe: {n * 4} bytes read and written per copy")
         del src, dst
     masks = torch.from_numpy(T.standard_masks(spec.ny, spec.nx, scale=spec.ny / 256)).cuda()
+    streaming = args.workload == "streaming"
     if args.workload == "precision":
         masks = torch.from_numpy(np.stack([T.disk_mask(64, 64, 24, inner=8),
                                            T.standard_masks(64, 64, 0.25)[0]])).cuda()
@@ -153,16 +162,24 @@ def main():
     plan = tacaw.Plan(spec.n_probe, spec.ny, spec.nx, spec.n_frames, L, H, masks=masks,
                       transform=args.form, in_dtype=spec.dtype, time_kernels=True, stream=stream,
                       dt_fs=dt_fs, omega_half=M)
+    pieces = [(f0, min(spec.n_frames, f0 + args.push_frames))
+              for f0 in range(0, spec.n_frames, args.push_frames)] if streaming else [(0, spec.n_frames)]
     n_om = plan.n_omega
     S = torch.empty((n_om, spec.ny, spec.nx), dtype=torch.float64, device="cuda")
     D = torch.empty((masks.shape[0], n_om), dtype=torch.float64, device="cuda")
     Dp = torch.empty((masks.shape[0], spec.n_probe, n_om), dtype=torch.float64, device="cuda")
 
-    def step():
+    def step(measure=False):
         plan.reset()
-        plan.push(psi)
+        k_ms = 0.0
+        for f0, f1 in pieces:
+            plan.push(psi[:, f0:f1])
+            if streaming and measure:  # sum the chunk-kernel durations of the pushes
+                t = plan.info()["last_chunk_kernel_ms"]
+                k_ms += t if t > 0 else 0.0  # -1: this push completed no chunk
         plan.finalize(S)
         plan.detector_spectra(per_probe=True, out=D, out_p=Dp)
+        return k_ms
 
     for i in range(args.warmup):
         step()
@@ -175,9 +192,13 @@ def main():
     e0.record(stream)
     for i in range(args.steps):
         step()
-        kernel_ms.append(plan.info()["last_chunk_kernel_ms"])  # waits for this step's kernel
+        if not streaming:  # waits for this step's chunk kernel
+            kernel_ms.append(plan.info()["last_chunk_kernel_ms"])
     e1.record(stream)
     torch.cuda.synchronize()
+    if streaming:  # one more (untimed) step that reads the kernel time after every push
+        kernel_ms.append(step(measure=True))
+        torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     log(f"timed {args.steps} steps: {ms:.3f} ms/step; chunk kernel {np.mean(kernel_ms):.3f} ms")
 
@@ -207,6 +228,7 @@ def main():
             "workload": f"{spec.n_probe} probes x {spec.n_frames} frames x {spec.ny}x{spec.nx} {spec.dtype}, "
                         f"Welch L={L} H={H} periodic Hann, global mean, {masks.shape[0]} detector masks, "
                         f"transform {args.form}"
+                        + (f", pushed in pieces of {args.push_frames} frames" if streaming else "")
                         + (f", energy window |E| <= {args.roi_mev:g} meV ({n_om} bins)" if M else ""),
             "probes": spec.n_probe, "frames": spec.n_frames, "ny": spec.ny, "nx": spec.nx,
             "seg_len": L, "hop": H, "n_omega": n_om, "exit_wave_bytes": b_alg,

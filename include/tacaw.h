@@ -111,9 +111,10 @@ typedef struct {
                           /* rows, and the DFT-GEMM form computes only these rows.   */
 } tacaw_plan_desc;
 
-/* flags: record HIP events around the chunk kernel of every push; the last
- * duration is reported in tacaw_plan_info.last_chunk_kernel_ms (reading it
- * synchronizes with the plan's stream). */
+/* flags: record HIP events around the chunk kernel of every push; the duration
+ * of the last push's kernel is reported in tacaw_plan_info.last_chunk_kernel_ms
+ * (reading it synchronizes with the plan's stream; -1 if that push completed no
+ * chunk). */
 #define TACAW_FLAG_TIME_KERNELS 1
 
 typedef struct {
@@ -127,7 +128,7 @@ typedef struct {
   double window_sum_sq;   /* sum_t w(t)^2                                            */
   int32_t tile_pixels;    /* pixels per workgroup tile of the push kernel            */
   int32_t reserved;
-  double last_chunk_kernel_ms; /* duration of the last push's chunk kernel (flag set) */
+  double last_chunk_kernel_ms; /* last push's chunk kernel in ms (flag set), or -1   */
 } tacaw_plan_info;
 
 /* Create a plan: validates desc on the host (no HIP call on failure), then

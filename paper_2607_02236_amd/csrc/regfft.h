@@ -57,29 +57,39 @@ __host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// t = w * b with w = exp(-2 pi i K / M) (compile-time), then (a, b) <- (a + t, a - t)
+// (a, b) <- (a + w b, a - w b) with w = exp(-2 pi i K / M) (compile-time).
+// A general twiddle is applied in factored form, w b = f u with f = cos (or sin)
+// and u = b rotated by the tangent (or cotangent) of the angle, so the butterfly
+// is 2 + 4 fused multiply-adds instead of 4 + 4 operations; |tan| <= 1 keeps the
+// rounding of u at one unit of u.
 template <int K, int M>
 __host__ __device__ __forceinline__ void bfly(float2& a, float2& b) {
   constexpr int Kr = K % M;
-  float2 t;
+  const float2 v = a;
   if constexpr (Kr == 0) {
-    t = b;
-  } else if constexpr (4 * Kr == M) {  // -i
-    t = make_float2(b.y, -b.x);
-  } else if constexpr (8 * Kr == M) {  // (1 - i) / sqrt(2)
-    constexpr float h = 0.70710678118654752440f;
-    t = make_float2((b.x + b.y) * h, (b.y - b.x) * h);
-  } else if constexpr (8 * Kr == 3 * M) {  // (-1 - i) / sqrt(2)
-    constexpr float h = 0.70710678118654752440f;
-    t = make_float2((b.y - b.x) * h, -(b.x + b.y) * h);
+    a = make_float2(v.x + b.x, v.y + b.y);
+    b = make_float2(v.x - b.x, v.y - b.y);
+  } else if constexpr (4 * Kr == M) {  // w = -i: w b = (b.y, -b.x)
+    a = make_float2(v.x + b.y, v.y - b.x);
+    b = make_float2(v.x - b.y, v.y + b.x);
   } else {
-    constexpr float c = (float)ct_cos2pi(Kr, M);
-    constexpr float s = -(float)ct_sin2pi(Kr, M);
-    t = make_float2(c * b.x - s * b.y, c * b.y + s * b.x);
+    constexpr double cd = ct_cos2pi(Kr, M);
+    constexpr double sd = -ct_sin2pi(Kr, M);  // w = cd + i sd
+    constexpr bool by_cos = (cd < 0 ? -cd : cd) >= (sd < 0 ? -sd : sd);
+    float2 u;
+    float f;
+    if constexpr (by_cos) {  // w b = cd (b + i (sd/cd) b)
+      constexpr float r = (float)(sd / cd);
+      f = (float)cd;
+      u = make_float2(__builtin_fmaf(-r, b.y, b.x), __builtin_fmaf(r, b.x, b.y));
+    } else {  // w b = sd ((cd/sd) b + i b)
+      constexpr float r = (float)(cd / sd);
+      f = (float)sd;
+      u = make_float2(__builtin_fmaf(r, b.x, -b.y), __builtin_fmaf(r, b.y, b.x));
+    }
+    a = make_float2(__builtin_fmaf(f, u.x, v.x), __builtin_fmaf(f, u.y, v.y));
+    b = make_float2(__builtin_fmaf(-f, u.x, v.x), __builtin_fmaf(-f, u.y, v.y));
   }
-  float2 u = a;
-  a = make_float2(u.x + t.x, u.y + t.y);
-  b = make_float2(u.x - t.x, u.y - t.y);
 }
 
 // x <- x * exp(-2 pi i K / M) with K, M compile-time

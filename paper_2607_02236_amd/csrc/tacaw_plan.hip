@@ -605,6 +605,7 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
                     "operand scale pre-pass"));
   }
   // 2. every chunk completed by this push
+  P->timed = false;
   if (s_hi > s_lo) {
     SegArgs g{};
     g.in = frames;
