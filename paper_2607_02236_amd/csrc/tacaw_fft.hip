@@ -70,6 +70,13 @@ template <>
 struct FftShape<1024> {
   static constexpr int N1 = 16, W = 8;
 };
+// L = 200 (the chunk length of the paper's worked example): 10-point DFTs
+// (prime-factor 2 x 5) in both passes; 32 pixels so that a wave's 64 lanes hold
+// two pass-2 roles of the same fold half
+template <>
+struct FftShape<200> {
+  static constexpr int N1 = 10, W = 32;
+};
 
 // Pass 2 for N2 > N1: the N2-point DFT of one k1 is shared by G = N2 / N1
 // threads. Thread g computes the outputs k2 = G r + g (r < N1) from
@@ -446,7 +453,8 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
         const int n_om = a.n_om;
         double* out = a.dpart + ((int64_t)slot * a.n_probes + i) * a.n_det * n_om;
         for (int r = tid; r < n_om; r += NT) {
-          const int m = (r - a.roi_half) & (L - 1);  // output row r holds bin m
+          int m = r - a.roi_half;  // output row r holds bin m
+          if (m < 0) m += L;
           double pv[W];
 #pragma unroll
           for (int x = 0; x < W; ++x) pv[x] = sp[m * W + x];
@@ -468,7 +476,8 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
 #pragma unroll
     for (int t = 0; t < N1; ++t) {
       const int m = (G == 1) ? (j + N2 * (t / N2)) + N1 * (t % N2) : k1g + N1 * (G * t + gg);
-      const int row = (m + a.roi_half) & (L - 1);  // rows >= n_om lie outside the energy window
+      int row = m + a.roi_half;  // rows >= n_om lie outside the energy window
+      if (row >= L) row -= L;
       if (row < a.n_om) {
         double* sp = a.S + (int64_t)row * n_k + k;
         *sp += acc[t];
@@ -511,13 +520,14 @@ void seg_fft_split(int L, int* n1, int* n2) {
     case 256: a = FftShape<256>::N1; break;
     case 512: a = FftShape<512>::N1; break;
     case 1024: a = FftShape<1024>::N1; break;
+    case 200: a = FftShape<200>::N1; break;
   }
   *n1 = a;
   *n2 = a ? L / a : 0;
 }
 
 bool seg_fft_supported(int L) {
-  return L == 64 || L == 128 || L == 256 || L == 512 || L == 1024;
+  return L == 64 || L == 128 || L == 256 || L == 512 || L == 1024 || L == 200;
 }
 
 int seg_fft_tile_pixels(int L) {
@@ -527,6 +537,7 @@ int seg_fft_tile_pixels(int L) {
     case 256: return FftShape<256>::W;
     case 512: return FftShape<512>::W;
     case 1024: return FftShape<1024>::W;
+    case 200: return FftShape<200>::W;
   }
   return 0;
 }
@@ -539,6 +550,7 @@ hipError_t launch_seg_fft(int L, int in_dtype, bool sub64, const SegArgs& a, int
     case 256: return launch_l<256>(in_dtype, sub64, a, n_tiles, st);
     case 512: return launch_l<512>(in_dtype, sub64, a, n_tiles, st);
     case 1024: return launch_l<1024>(in_dtype, sub64, a, n_tiles, st);
+    case 200: return launch_l<200>(in_dtype, sub64, a, n_tiles, st);
   }
   return hipErrorInvalidValue;
 }

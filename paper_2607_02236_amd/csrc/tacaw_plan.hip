@@ -259,8 +259,10 @@ int tacaw_plan_check(const tacaw_plan_desc* d) {
   if (d->ny < 1 || d->nx < 1) return fail(TACAW_ERR_INVALID_ARG, "ny and nx must be >= 1");
   if ((int64_t)d->ny * d->nx > (int64_t)1 << 30)
     return fail(TACAW_ERR_INVALID_ARG, "ny * nx must be <= 2^30");
-  if (!is_pow2(d->seg_len) || d->seg_len < 64 || d->seg_len > 1024)
-    return fail(TACAW_ERR_UNSUPPORTED, "seg_len must be a power of two in [64, 1024]");
+  if (!((is_pow2(d->seg_len) && d->seg_len >= 64 && d->seg_len <= 1024) || d->seg_len == 200))
+    return fail(TACAW_ERR_UNSUPPORTED, "seg_len must be a power of two in [64, 1024] or 200");
+  if (!is_pow2(d->seg_len) && d->transform != TACAW_FFT_F32)
+    return fail(TACAW_ERR_UNSUPPORTED, "seg_len 200 needs the FFT transform");
   if (d->hop < 1 || d->hop > d->seg_len)
     return fail(TACAW_ERR_INVALID_ARG, "hop must satisfy 1 <= hop <= seg_len");
   if (d->n_frames < d->seg_len)
@@ -760,6 +762,7 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   if (n_probes > 1 && pstride < 1) return fail(TACAW_ERR_INVALID_ARG, "probe_stride must be >= 1");
   if (P->H != P->L && 2 * P->H != P->L)
     return fail(TACAW_ERR_UNSUPPORTED, "backward supports hop = L or hop = L/2");
+  if (!is_pow2(P->L)) return fail(TACAW_ERR_UNSUPPORTED, "backward needs a power-of-two seg_len");
   if ((gD || gDp) && P->d.n_det == 0)
     return fail(TACAW_ERR_INVALID_ARG, "detector gradients need plan masks");
   int n1b = 0, n2b = 0;
