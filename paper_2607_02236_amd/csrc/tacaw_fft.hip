@@ -56,9 +56,6 @@ template <>
 struct FftShape<256> {
   static constexpr int N1 = 16, W = 16;
 };
-#ifndef TACAW_LEAN_RELOAD
-#define TACAW_LEAN_RELOAD 0  // 1: reload the overlapping half-chunk instead of keeping it
-#endif
 #ifndef TACAW_TILE_W512
 #define TACAW_TILE_W512 16  // pixels per workgroup at L = 512 (tuning parameter)
 #endif
@@ -132,9 +129,6 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
   constexpr int KROW = N2 * W + PADK;      // float2 per k1 row of the exchange tile
   static_assert(N1 % N2 == 0 || N2 % N1 == 0, "pass-2 split");
   static_assert(G == 1 || G == 2 || G == 4, "pass-2 split factor");
-  // LEAN with TACAW_LEAN_RELOAD: the overlapping half is loaded again (from the
-  // caches) instead of being kept in registers
-  constexpr bool RELOAD = LEAN && TACAW_LEAN_RELOAD;
 
   // two exchange tiles [k1][n2][px] used by alternate chunks, so one barrier per
   // chunk suffices; tile 0 is reused for the per-probe reductions
@@ -284,7 +278,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
           for (int n1 = 0; n1 < N1; ++n1)
             if (n1 >= lo) v[n1] = take(n1, pre[n1], cmode);
         };
-        if (!RELOAD && have_kept) {
+        if (have_kept) {
 #pragma unroll
           for (int n1 = 0; n1 < HALF; ++n1) v[n1] = kept[n1];
           if (track) take_pre(HALF, C1{});
@@ -299,7 +293,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
         // prefetch the next chunk's new samples (or the next probe's first chunk)
         if (s + 1 < a.s_hi) {
 #pragma unroll
-          for (int n1 = RELOAD ? 0 : HALF; n1 < N1; ++n1) pre[n1] = fetch_at(i, s + 1, n1);
+          for (int n1 = HALF; n1 < N1; ++n1) pre[n1] = fetch_at(i, s + 1, n1);
         } else if (i + 1 < a.n_probes) {
 #pragma unroll
           for (int n1 = 0; n1 < N1; ++n1) pre[n1] = fetch_at(i + 1, a.s_lo, n1);
@@ -327,10 +321,8 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
           else load_range(0, fetch_any, C2{});
         }
       }
-      if constexpr (!RELOAD) {
 #pragma unroll
-        for (int n1 = HALF; n1 < N1; ++n1) kept[n1 - HALF] = v[n1];
-      }
+      for (int n1 = HALF; n1 < N1; ++n1) kept[n1 - HALF] = v[n1];
       have_kept = true;
 
       // window (table stored per thread: s_win[n2 * N1 + n1] = w(N2 n1 + n2))

@@ -313,3 +313,27 @@ def test_seg_len_200_rejects_gemm_and_backward(tacaw):
         plan.backward(psi, gS=torch.zeros((200, 4, 4), dtype=torch.float64, device="cuda"))
     assert e.value.kind == "UNSUPPORTED"
     plan.close()
+
+
+@pytest.mark.parametrize("window", ["hann", "blackmanharris"])
+def test_leakage_tails_pointwise(tacaw, window):
+    # App. A compares windows by their leakage; the FP32 path must reproduce the
+    # tails bin by bin, not only in the L2 norm: tones half-way between bins on an
+    # elastic background, bins 4.5 .. 32.5 away from each tone
+    import scipy.signal
+
+    L, ny, nx = 512, 4, 8
+    t = np.arange(L)
+    nu = 40.5 + 13.0 * np.arange(ny * nx)  # one tone per pixel, all off-bin
+    x = 1.0 + 1e-3 * np.exp(2j * np.pi * np.outer(t, nu) / L)
+    psi = torch.from_numpy(x.astype(np.complex64).reshape(1, L, ny, nx))
+    w = O.window("hann", L) if window == "hann" else scipy.signal.get_window(window, L)
+    g = run_gpu(tacaw, psi, L, L, window=window if window == "hann" else w)
+    So, _ = O.tacaw_spectra(psi.numpy(), L, L, w)
+    worst = 0.0
+    for k in range(ny * nx):
+        for d in np.arange(4.5, 33.0, 1.0):
+            m = int(nu[k] + d) % L
+            worst = max(worst, abs(g["S"][m, k] - So[m, k]) / So[m, k])
+    say(f"{window} tails: worst pointwise rel err {worst:.2e}")
+    assert worst <= 1e-2
