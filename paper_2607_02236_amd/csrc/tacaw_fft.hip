@@ -440,23 +440,23 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
         sp[m * W + px] = acc[t];
       }
       __syncthreads();
-      const int slot = a.tile_slot[tile];
-      if (slot >= 0) {
-        const int n_om = a.n_om;
-        double* out = a.dpart + ((int64_t)slot * a.n_probes + i) * a.n_det * n_om;
-        for (int r = tid; r < n_om; r += NT) {
-          int m = r - a.roi_half;  // output row r holds bin m
-          if (m < 0) m += L;
-          double pv[W];
+      const int n_om = a.n_om;
+      const int32_t* slots = a.pair_slot + (int64_t)tile * a.n_det;
+      for (int r = tid; r < n_om; r += NT) {
+        int m = r - a.roi_half;  // output row r holds bin m
+        if (m < 0) m += L;
+        double pv[W];
 #pragma unroll
-          for (int x = 0; x < W; ++x) pv[x] = sp[m * W + x];
+        for (int x = 0; x < W; ++x) pv[x] = sp[m * W + x];
 #pragma unroll 1
-          for (int d = 0; d < a.n_det; ++d) {
-            double dsum = 0.0;
+        for (int d = 0; d < a.n_det; ++d) {
+          const int slot = slots[d];  // uniform; -1: this detector's mask is zero here
+          if (slot < 0) continue;
+          double dsum = 0.0;
 #pragma unroll
-            for (int x = 0; x < W; ++x) dsum += s_mask[d * W + x] * pv[x];
-            out[(int64_t)d * n_om + r] = dsum;  // cumulative over the launch's probes 0..i
-          }
+          for (int x = 0; x < W; ++x) dsum += s_mask[d * W + x] * pv[x];
+          // cumulative over the launch's probes 0..i
+          a.dpart[((int64_t)slot * a.n_probes + i) * n_om + r] = dsum;
         }
       }
     }
