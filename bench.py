@@ -95,9 +95,12 @@ def main():
                     choices=["realistic", "precision", "streaming"],
                     help="realistic: 64 probes x 2048 frames x 256^2 c64 (default); precision: "
                          "1 probe x 512 frames x 64^2 c128, one chunk of 512; streaming: "
-                         "--probes (default 2) x 4096 frames x 1024^2 c64, L=1024 H=512, "
+                         "--probes (default 16) x 4096 frames x 1024^2 c64, L=1024 H=512, "
                          "pushed in pieces of --push-frames frames through the plan's ring")
     ap.add_argument("--push-frames", type=int, default=256)
+    ap.add_argument("--resident-frames", type=int, default=512,
+                    help="streaming: frames held in HBM per probe; pushes cycle through them "
+                         "(4096 = the whole series)")
     ap.add_argument("--roi-mev", type=float, default=0.0,
                     help="keep only the energy window |E| <= this (0: all bins); the DFT-GEMM "
                          "form then computes only the window's rows")
@@ -124,15 +127,23 @@ def main():
         spec = T.config_precision(n_frames=512)
     elif args.workload == "streaming":
         L, H = 1024, 512
-        n_pr = args.probes if args.probes != 64 else 2
+        n_pr = args.probes if args.probes != 64 else 16
         spec = T.config_streaming(n_probe=n_pr, n_frames=4096, ny=1024, nx=1024)
     else:
         L, H = args.seg_len, args.seg_len // 2
         spec = T.config_realistic(n_probe=args.probes, n_frames=args.frames, ny=args.grid,
                                   nx=args.grid)
-    log(f"allocating {spec.nbytes / 1e9:.1f} GB of exit waves on the GPU")
-    psi = torch.empty((spec.n_probe, spec.n_frames, spec.ny, spec.nx), dtype=spec.torch_dtype,
-                      device="cuda")
+    streaming = args.workload == "streaming"
+    resident = spec
+    if streaming:
+        R = min(args.resident_frames, spec.n_frames)
+        if R % args.push_frames or spec.n_frames % args.push_frames:
+            sys.exit("--resident-frames and 4096 must be multiples of --push-frames")
+        resident = T.config_streaming(n_probe=spec.n_probe, n_frames=R, ny=spec.ny, nx=spec.nx)
+    log(f"allocating {resident.nbytes / 1e9:.1f} GB of exit waves on the GPU")
+    psi = torch.empty((resident.n_probe, resident.n_frames, spec.ny, spec.nx),
+                      dtype=spec.torch_dtype, device="cuda")
+    spec_gen, spec = spec, resident  # generate the resident frames
     t0 = time.time()
     for p in range(spec.n_probe):
         T.generate_into(spec, psi[p:p + 1], probes=[p], frame_chunk=256)
@@ -140,6 +151,7 @@ def main():
             torch.cuda.synchronize()
             log(f"generated probe {p + 1}/{spec.n_probe} ({time.time() - t0:.1f} s)")
     torch.cuda.synchronize()
+    spec = spec_gen
     if args.copy_probe_gib > 0:
         n = int(args.copy_probe_gib * (1 << 30)) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -150,7 +162,6 @@ def main():
         log(f"copy probe: {n * 4} bytes read and written per copy")
         del src, dst
     masks = torch.from_numpy(T.standard_masks(spec.ny, spec.nx, scale=spec.ny / 256)).cuda()
-    streaming = args.workload == "streaming"
     if args.workload == "precision":
         masks = torch.from_numpy(np.stack([T.disk_mask(64, 64, 24, inner=8),
                                            T.standard_masks(64, 64, 0.25)[0]])).cuda()
@@ -162,6 +173,7 @@ def main():
     plan = tacaw.Plan(spec.n_probe, spec.ny, spec.nx, spec.n_frames, L, H, masks=masks,
                       transform=args.form, in_dtype=spec.dtype, time_kernels=True, stream=stream,
                       dt_fs=dt_fs, omega_half=M)
+    R = psi.shape[1]
     pieces = [(f0, min(spec.n_frames, f0 + args.push_frames))
               for f0 in range(0, spec.n_frames, args.push_frames)] if streaming else [(0, spec.n_frames)]
     n_om = plan.n_omega
@@ -173,7 +185,7 @@ def main():
         plan.reset()
         k_ms = 0.0
         for f0, f1 in pieces:
-            plan.push(psi[:, f0:f1])
+            plan.push(psi[:, f0 % R:f0 % R + (f1 - f0)])
             if streaming and measure:  # sum the chunk-kernel durations of the pushes
                 t = plan.info()["last_chunk_kernel_ms"]
                 k_ms += t if t > 0 else 0.0  # -1: this push completed no chunk
@@ -223,7 +235,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded generator: elastic 1 + 8 Lorentzian-line tones of 1e-3/sqrt(8) per pixel + 1e-5 noise)",
+        "data": "synthetic (seeded generator: elastic 1 + 8 Lorentzian-line tones of 1e-3/sqrt(8) per pixel + 1e-5 noise)"
+                + (f"; frames repeat with period {R} (resident block)" if R < spec.n_frames else ""),
         "config": {
             "workload": f"{spec.n_probe} probes x {spec.n_frames} frames x {spec.ny}x{spec.nx} {spec.dtype}, "
                         f"Welch L={L} H={H} periodic Hann, global mean, {masks.shape[0]} detector masks, "

@@ -80,7 +80,8 @@ typedef struct {
   int32_t n_probe;        /* probes (scan positions) in this plan, >= 1              */
   int32_t ny, nx;         /* reciprocal-space grid, ny * nx pixels                   */
   int64_t n_frames;       /* frames that will be pushed per probe (N_t >= seg_len)   */
-  int32_t seg_len;        /* L: power of two, 64 <= L <= 1024                        */
+  int32_t seg_len;        /* L: power of two in [64, 1024], or 200 (Sec. III.A's     */
+                          /* chunk length; FFT transform, forward only)              */
   int32_t hop;            /* H = L / nu with integer division, 1 <= H <= L           */
   int32_t window;         /* TACAW_WIN_*                                             */
   double window_param;    /* r for HANN_WIDTH (> 0), alpha for TUKEY ([0, 1])        */

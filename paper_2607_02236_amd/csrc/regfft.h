@@ -1,4 +1,5 @@
-// In-register complex DFTs of size 8, 16 and 32 for one thread, FP32.
+// In-register complex DFTs for one thread, FP32: sizes 2^k (radix 2) and
+// 5 * 2^k (prime-factor split into 2^k- and 5-point DFTs).
 //
 // Radix-2 decimation in time on a fully unrolled register array: the input is
 // read in bit-reversed order (free: register renaming), every butterfly's
@@ -152,20 +153,76 @@ struct FftStages {
   }
 };
 
-// In-place forward DFT of N values in natural order (input and output).
+// 5-point DFT X(k) = sum_n x(n) exp(-2 pi i n k / 5): with a1 = x1 + x4, a2 = x2 + x3,
+// b1 = x1 - x4, b2 = x2 - x3, the pairs X(1), X(4) and X(2), X(3) share their real
+// combinations x0 + c a1 + c' a2 and differ in the sign of i (s b1 +- s' b2).
+__host__ __device__ __forceinline__ void dft5(float2& x0, float2& x1, float2& x2, float2& x3,
+                                              float2& x4) {
+  constexpr float c1 = (float)ct_cos2pi(1, 5), c2 = (float)ct_cos2pi(2, 5);
+  constexpr float s1 = (float)ct_sin2pi(1, 5), s2 = (float)ct_sin2pi(2, 5);
+  const float2 a1 = make_float2(x1.x + x4.x, x1.y + x4.y);
+  const float2 a2 = make_float2(x2.x + x3.x, x2.y + x3.y);
+  const float2 b1 = make_float2(x1.x - x4.x, x1.y - x4.y);
+  const float2 b2 = make_float2(x2.x - x3.x, x2.y - x3.y);
+  const float2 m1 = make_float2(__builtin_fmaf(c2, a2.x, __builtin_fmaf(c1, a1.x, x0.x)),
+                                __builtin_fmaf(c2, a2.y, __builtin_fmaf(c1, a1.y, x0.y)));
+  const float2 m2 = make_float2(__builtin_fmaf(c1, a2.x, __builtin_fmaf(c2, a1.x, x0.x)),
+                                __builtin_fmaf(c1, a2.y, __builtin_fmaf(c2, a1.y, x0.y)));
+  const float2 n1 = make_float2(__builtin_fmaf(s2, b2.x, s1 * b1.x), __builtin_fmaf(s2, b2.y, s1 * b1.y));
+  const float2 n2 = make_float2(__builtin_fmaf(-s1, b2.x, s2 * b1.x), __builtin_fmaf(-s1, b2.y, s2 * b1.y));
+  x0 = make_float2(x0.x + a1.x + a2.x, x0.y + a1.y + a2.y);
+  // X(1) = m1 - i n1, X(4) = m1 + i n1, X(2) = m2 - i n2, X(3) = m2 + i n2
+  x1 = make_float2(m1.x + n1.y, m1.y - n1.x);
+  x4 = make_float2(m1.x - n1.y, m1.y + n1.x);
+  x2 = make_float2(m2.x + n2.y, m2.y - n2.x);
+  x3 = make_float2(m2.x - n2.y, m2.y + n2.x);
+}
+
+constexpr int inv_mod(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 1;
+}
+
+// In-place forward DFT of N values in natural order (input and output): radix-2
+// for powers of two; for N = 5 P (P a power of two, coprime to 5) the
+// prime-factor (Good-Thomas) split needs no twiddles: x(n) with
+// n = (5 n_p + P n_q) mod N goes through P-point DFTs over n_p and 5-point DFTs
+// over n_q, and lands at k = (5 (5^-1 mod P) k_p + P (P^-1 mod 5) k_q) mod N.
 template <int N>
 __host__ __device__ __forceinline__ void dft_inplace(float2 (&a)[N]) {
-  static_assert((N & (N - 1)) == 0 && N >= 2, "power of two");
+  if constexpr ((N & (N - 1)) == 0) {
+    static_assert(N >= 2, "size");
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    const int j = bitrev<N>(i);
-    if (j > i) {
-      float2 t = a[i];
-      a[i] = a[j];
-      a[j] = t;
+    for (int i = 0; i < N; ++i) {
+      const int j = bitrev<N>(i);
+      if (j > i) {
+        float2 t = a[i];
+        a[i] = a[j];
+        a[j] = t;
+      }
     }
+    FftStages<N, 1>::run(a);
+  } else {
+    constexpr int Q = 5, P = N / Q;
+    static_assert(N % Q == 0 && (P & (P - 1)) == 0 && P >= 1, "N = 5 * 2^k");
+    float2 b[Q][P];  // b[n_q][n_p]
+#pragma unroll
+    for (int nq = 0; nq < Q; ++nq)
+#pragma unroll
+      for (int np = 0; np < P; ++np) b[nq][np] = a[(Q * np + P * nq) % N];
+    if constexpr (P > 1) {
+#pragma unroll
+      for (int nq = 0; nq < Q; ++nq) dft_inplace<P>(b[nq]);
+    }
+#pragma unroll
+    for (int kp = 0; kp < P; ++kp) dft5(b[0][kp], b[1][kp], b[2][kp], b[3][kp], b[4][kp]);
+    constexpr int ep = Q * (P > 1 ? inv_mod(Q % P, P) : 0), eq = P * inv_mod(P % Q, Q);
+#pragma unroll
+    for (int kq = 0; kq < Q; ++kq)
+#pragma unroll
+      for (int kp = 0; kp < P; ++kp) a[(ep * kp + eq * kq) % N] = b[kq][kp];
   }
-  FftStages<N, 1>::run(a);
 }
 
 }  // namespace tacaw

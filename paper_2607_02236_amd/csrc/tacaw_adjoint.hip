@@ -86,7 +86,8 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
     float Gt[N1];
 #pragma unroll
     for (int t = 0; t < N1; ++t) {
-      const int r = (F::bin(t, n2) + a.roi_half) & (L - 1);  // output row of the bin
+      int r = F::bin(t, n2) + a.roi_half;  // output row of the bin
+      if (r >= L) r -= L;
       const int n_om = a.n_om;
       double g = 0.0;
       if (r < n_om) {

@@ -121,38 +121,42 @@ hipError_t launch_ring_store(const void* in, int in_dtype, int64_t pstride, int6
   return hipGetLastError();
 }
 
-// Per-probe detector spectra from the cumulative tile partials:
-// Dp[d][probe0 + i][m] += sum_slot (part[slot][i][d][m] - part[slot][i-1][d][m]).
-// Block (m-range, d, g) sums the slots of group g, reads every partial once and
-// adds its per-probe differences atomically (groups run in parallel).
-constexpr int kDpartGroups = 64;
-__global__ void dpart_reduce_kernel(const double* part, int32_t n_active, int32_t n_probes,
-                                    int32_t n_det, int32_t L, int32_t probe0, int32_t n_probe_total,
-                                    double* Dp) {
+// Per-probe detector spectra from the cumulative (tile, detector) partials:
+// Dp[d][probe0 + i][m] += sum over the slots s of detector d of
+// (part[s][i][m] - part[s][i-1][m]). Block (m-range, d, g) sums a group of at
+// most `per` slots, reads every partial once and adds its per-probe differences
+// atomically (groups run in parallel).
+__global__ void dpart_reduce_kernel(const double* part, DetSlots so, int32_t per,
+                                    int32_t n_probes, int32_t n_om, int32_t probe0,
+                                    int32_t n_probe_total, double* Dp) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   const int d = blockIdx.y;
   const int g = blockIdx.z;
-  if (m >= L) return;
-  const int per = (n_active + kDpartGroups - 1) / kDpartGroups;
-  const int s0 = g * per, s1 = min(n_active, s0 + per);
+  if (m >= n_om) return;
+  const int s0 = so.off[d] + g * per, s1 = min(so.off[d + 1], s0 + per);
   if (s0 >= s1) return;
-  const int64_t per_slot = (int64_t)n_probes * n_det * L;
+  const int64_t per_slot = (int64_t)n_probes * n_om;
   double prev = 0.0;
   for (int i = 0; i < n_probes; ++i) {
-    const double* base = part + ((int64_t)i * n_det + d) * L + m;
+    const double* base = part + (int64_t)i * n_om + m;
     double cur = 0.0;
     for (int s = s0; s < s1; ++s) cur += base[s * per_slot];
-    atomicAdd(&Dp[((int64_t)d * n_probe_total + probe0 + i) * L + m], cur - prev);
+    atomicAdd(&Dp[((int64_t)d * n_probe_total + probe0 + i) * n_om + m], cur - prev);
     prev = cur;
   }
 }
 
-hipError_t launch_dpart_reduce(const double* dpart, int32_t n_active, int32_t n_probes,
-                               int32_t n_det, int32_t L, int32_t probe0, int32_t n_probe_total,
+hipError_t launch_dpart_reduce(const double* dpart, const DetSlots& so, int32_t n_probes,
+                               int32_t n_det, int32_t n_om, int32_t probe0, int32_t n_probe_total,
                                double* Dp, hipStream_t st) {
-  dim3 g((L + 127) / 128, n_det, kDpartGroups);
-  hipLaunchKernelGGL(dpart_reduce_kernel, g, dim3(128), 0, st, dpart, n_active, n_probes, n_det,
-                     L, probe0, n_probe_total, Dp);
+  int most = 0;
+  for (int d = 0; d < n_det; ++d) most = max(most, so.off[d + 1] - so.off[d]);
+  if (most == 0) return hipSuccess;
+  int per = 8;  // slots per block: enough blocks to fill the chip, few atomics per value
+  if ((most + per - 1) / per > 1024) per = (most + 1023) / 1024;
+  dim3 g((n_om + 127) / 128, n_det, (most + per - 1) / per);
+  hipLaunchKernelGGL(dpart_reduce_kernel, g, dim3(128), 0, st, dpart, so, per, n_probes, n_om,
+                     probe0, n_probe_total, Dp);
   return hipGetLastError();
 }
 

@@ -56,9 +56,6 @@ template <>
 struct FftShape<256> {
   static constexpr int N1 = 16, W = 16;
 };
-#ifndef TACAW_LEAN_RELOAD
-#define TACAW_LEAN_RELOAD 0  // 1: reload the overlapping half-chunk instead of keeping it
-#endif
 #ifndef TACAW_TILE_W512
 #define TACAW_TILE_W512 16  // pixels per workgroup at L = 512 (tuning parameter)
 #endif
@@ -69,6 +66,13 @@ struct FftShape<512> {
 template <>
 struct FftShape<1024> {
   static constexpr int N1 = 16, W = 8;
+};
+// L = 200 (the chunk length of the paper's worked example): 10-point DFTs
+// (prime-factor 2 x 5) in both passes; 32 pixels so that a wave's 64 lanes hold
+// two pass-2 roles of the same fold half
+template <>
+struct FftShape<200> {
+  static constexpr int N1 = 10, W = 32;
 };
 
 // Pass 2 for N2 > N1: the N2-point DFT of one k1 is shared by G = N2 / N1
@@ -125,9 +129,6 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
   constexpr int KROW = N2 * W + PADK;      // float2 per k1 row of the exchange tile
   static_assert(N1 % N2 == 0 || N2 % N1 == 0, "pass-2 split");
   static_assert(G == 1 || G == 2 || G == 4, "pass-2 split factor");
-  // LEAN with TACAW_LEAN_RELOAD: the overlapping half is loaded again (from the
-  // caches) instead of being kept in registers
-  constexpr bool RELOAD = LEAN && TACAW_LEAN_RELOAD;
 
   // two exchange tiles [k1][n2][px] used by alternate chunks, so one barrier per
   // chunk suffices; tile 0 is reused for the per-probe reductions
@@ -277,7 +278,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
           for (int n1 = 0; n1 < N1; ++n1)
             if (n1 >= lo) v[n1] = take(n1, pre[n1], cmode);
         };
-        if (!RELOAD && have_kept) {
+        if (have_kept) {
 #pragma unroll
           for (int n1 = 0; n1 < HALF; ++n1) v[n1] = kept[n1];
           if (track) take_pre(HALF, C1{});
@@ -292,7 +293,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
         // prefetch the next chunk's new samples (or the next probe's first chunk)
         if (s + 1 < a.s_hi) {
 #pragma unroll
-          for (int n1 = RELOAD ? 0 : HALF; n1 < N1; ++n1) pre[n1] = fetch_at(i, s + 1, n1);
+          for (int n1 = HALF; n1 < N1; ++n1) pre[n1] = fetch_at(i, s + 1, n1);
         } else if (i + 1 < a.n_probes) {
 #pragma unroll
           for (int n1 = 0; n1 < N1; ++n1) pre[n1] = fetch_at(i + 1, a.s_lo, n1);
@@ -320,10 +321,8 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
           else load_range(0, fetch_any, C2{});
         }
       }
-      if constexpr (!RELOAD) {
 #pragma unroll
-        for (int n1 = HALF; n1 < N1; ++n1) kept[n1 - HALF] = v[n1];
-      }
+      for (int n1 = HALF; n1 < N1; ++n1) kept[n1 - HALF] = v[n1];
       have_kept = true;
 
       // window (table stored per thread: s_win[n2 * N1 + n1] = w(N2 n1 + n2))
@@ -441,22 +440,23 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
         sp[m * W + px] = acc[t];
       }
       __syncthreads();
-      const int slot = a.tile_slot[tile];
-      if (slot >= 0) {
-        const int n_om = a.n_om;
-        double* out = a.dpart + ((int64_t)slot * a.n_probes + i) * a.n_det * n_om;
-        for (int r = tid; r < n_om; r += NT) {
-          const int m = (r - a.roi_half) & (L - 1);  // output row r holds bin m
-          double pv[W];
+      const int n_om = a.n_om;
+      const int32_t* slots = a.pair_slot + (int64_t)tile * a.n_det;
+      for (int r = tid; r < n_om; r += NT) {
+        int m = r - a.roi_half;  // output row r holds bin m
+        if (m < 0) m += L;
+        double pv[W];
 #pragma unroll
-          for (int x = 0; x < W; ++x) pv[x] = sp[m * W + x];
+        for (int x = 0; x < W; ++x) pv[x] = sp[m * W + x];
 #pragma unroll 1
-          for (int d = 0; d < a.n_det; ++d) {
-            double dsum = 0.0;
+        for (int d = 0; d < a.n_det; ++d) {
+          const int slot = slots[d];  // uniform; -1: this detector's mask is zero here
+          if (slot < 0) continue;
+          double dsum = 0.0;
 #pragma unroll
-            for (int x = 0; x < W; ++x) dsum += s_mask[d * W + x] * pv[x];
-            out[(int64_t)d * n_om + r] = dsum;  // cumulative over the launch's probes 0..i
-          }
+          for (int x = 0; x < W; ++x) dsum += s_mask[d * W + x] * pv[x];
+          // cumulative over the launch's probes 0..i
+          a.dpart[((int64_t)slot * a.n_probes + i) * n_om + r] = dsum;
         }
       }
     }
@@ -468,7 +468,8 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
 #pragma unroll
     for (int t = 0; t < N1; ++t) {
       const int m = (G == 1) ? (j + N2 * (t / N2)) + N1 * (t % N2) : k1g + N1 * (G * t + gg);
-      const int row = (m + a.roi_half) & (L - 1);  // rows >= n_om lie outside the energy window
+      int row = m + a.roi_half;  // rows >= n_om lie outside the energy window
+      if (row >= L) row -= L;
       if (row < a.n_om) {
         double* sp = a.S + (int64_t)row * n_k + k;
         *sp += acc[t];
@@ -511,13 +512,14 @@ void seg_fft_split(int L, int* n1, int* n2) {
     case 256: a = FftShape<256>::N1; break;
     case 512: a = FftShape<512>::N1; break;
     case 1024: a = FftShape<1024>::N1; break;
+    case 200: a = FftShape<200>::N1; break;
   }
   *n1 = a;
   *n2 = a ? L / a : 0;
 }
 
 bool seg_fft_supported(int L) {
-  return L == 64 || L == 128 || L == 256 || L == 512 || L == 1024;
+  return L == 64 || L == 128 || L == 256 || L == 512 || L == 1024 || L == 200;
 }
 
 int seg_fft_tile_pixels(int L) {
@@ -527,6 +529,7 @@ int seg_fft_tile_pixels(int L) {
     case 256: return FftShape<256>::W;
     case 512: return FftShape<512>::W;
     case 1024: return FftShape<1024>::W;
+    case 200: return FftShape<200>::W;
   }
   return 0;
 }
@@ -539,6 +542,7 @@ hipError_t launch_seg_fft(int L, int in_dtype, bool sub64, const SegArgs& a, int
     case 256: return launch_l<256>(in_dtype, sub64, a, n_tiles, st);
     case 512: return launch_l<512>(in_dtype, sub64, a, n_tiles, st);
     case 1024: return launch_l<1024>(in_dtype, sub64, a, n_tiles, st);
+    case 200: return launch_l<200>(in_dtype, sub64, a, n_tiles, st);
   }
   return hipErrorInvalidValue;
 }

@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
       // cumulative detector partials through LDS, two halves of the rows
       double* sd = reinterpret_cast<double*>(bst);  // needs L/2 * 32 doubles
       static_assert(sizeof(bst) >= (size_t)L / 2 * kGemmPx * 8, "LDS for partials");
-      const int slot = a.tile_slot[tile];
+      const int32_t* slots = a.pair_slot + (int64_t)tile * a.n_det;
       const int hrows = (n_om + 1) / 2;  // <= L/2
       for (int hb = 0; hb < 2; ++hb) {
         __syncthreads();
@@ -213,16 +213,16 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
           }
         }
         __syncthreads();
-        if (slot >= 0) {
-          double* out = a.dpart + ((int64_t)slot * a.n_probes + i) * a.n_det * n_om;
-          const int r0 = hb * hrows, nr = hb ? n_om - hrows : hrows;
-          for (int rr = tid; rr < nr; rr += NT) {
-            for (int d = 0; d < a.n_det; ++d) {
-              double dsum = 0.0;
+        const int r0 = hb * hrows, nr = hb ? n_om - hrows : hrows;
+        for (int rr = tid; rr < nr; rr += NT) {
+          for (int d = 0; d < a.n_det; ++d) {
+            const int slot = slots[d];  // -1: this detector's mask is zero on the tile
+            if (slot < 0) continue;
+            double dsum = 0.0;
 #pragma unroll
-              for (int x = 0; x < kGemmPx; ++x) dsum += s_mask[d * kGemmPx + x] * sd[rr * kGemmPx + x];
-              out[(int64_t)d * n_om + r0 + rr] = dsum;  // cumulative over probes 0..i
-            }
+            for (int x = 0; x < kGemmPx; ++x) dsum += s_mask[d * kGemmPx + x] * sd[rr * kGemmPx + x];
+            // cumulative over probes 0..i
+            a.dpart[((int64_t)slot * a.n_probes + i) * n_om + r0 + rr] = dsum;
           }
         }
       }

@@ -35,8 +35,9 @@ struct SegArgs {
   int32_t roi_half;        // energy window M (0 = all bins); bin m -> row (m + M) mod L
   int32_t n_det;           // per-probe detector partials (0 = off)
   const double* masks;     // [n_det][n_k]
-  const int32_t* tile_slot;// [n_tiles] slot in dpart, -1 if no mask touches the tile
-  double* dpart;           // [n_active][n_probes][n_det][n_om]
+  const int32_t* pair_slot;// [n_tiles][n_det] slot in dpart of (tile, detector), -1 if the
+                           // detector's mask is zero on the tile; slots are grouped by detector
+  double* dpart;           // [n_pairs][n_probes][n_om]
   const float* gscale;     // GEMM form: [n_probe][n_k] power-of-two scale of psi - mu
 };
 
@@ -68,8 +69,12 @@ hipError_t launch_ring_store(const void* in, int in_dtype, int64_t pstride, int6
                              int64_t push_begin, int64_t f_lo, int64_t f_hi, int32_t probe0,
                              int32_t n_probes, int32_t n_slots, int32_t L, int32_t n_k,
                              void* ring, hipStream_t st);
-hipError_t launch_dpart_reduce(const double* dpart, int32_t n_active, int32_t n_probes,
-                               int32_t n_det, int32_t L, int32_t probe0, int32_t n_probe_total,
+// det_off[d] .. det_off[d + 1]: the dpart slots of detector d (n_det + 1 entries)
+struct DetSlots {
+  int32_t off[kMaxDet + 1];
+};
+hipError_t launch_dpart_reduce(const double* dpart, const DetSlots& slots, int32_t n_probes,
+                               int32_t n_det, int32_t n_om, int32_t probe0, int32_t n_probe_total,
                                double* Dp, hipStream_t st);
 
 struct CorrArgs {

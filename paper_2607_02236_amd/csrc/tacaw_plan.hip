@@ -166,7 +166,8 @@ struct tacaw_plan_s {
   int esz = 8;
   int state = 0;  // 0 open, 1 finalized
   int64_t dropped = 0;
-  int n_active = 0;
+  int n_pairs = 0;          // (tile, detector) pairs with a non-zero mask
+  DetSlots det_slots{};
   int n_slots = 0;
   std::vector<int64_t> cursor;
   std::vector<int> slot_owner;
@@ -181,7 +182,7 @@ struct tacaw_plan_s {
   double2* xs = nullptr;    // [P][3][n_k]
   double* S = nullptr;      // [n_om][n_k]
   double* masks = nullptr;  // [n_det][n_k]
-  int32_t* tile_slot = nullptr;
+  int32_t* pair_slot = nullptr;  // [n_tiles][n_det]
   double* Dp = nullptr;     // [n_det][P][n_om]
   double* dpart = nullptr;
   int64_t dpart_bytes = 0;
@@ -259,8 +260,10 @@ int tacaw_plan_check(const tacaw_plan_desc* d) {
   if (d->ny < 1 || d->nx < 1) return fail(TACAW_ERR_INVALID_ARG, "ny and nx must be >= 1");
   if ((int64_t)d->ny * d->nx > (int64_t)1 << 30)
     return fail(TACAW_ERR_INVALID_ARG, "ny * nx must be <= 2^30");
-  if (!is_pow2(d->seg_len) || d->seg_len < 64 || d->seg_len > 1024)
-    return fail(TACAW_ERR_UNSUPPORTED, "seg_len must be a power of two in [64, 1024]");
+  if (!((is_pow2(d->seg_len) && d->seg_len >= 64 && d->seg_len <= 1024) || d->seg_len == 200))
+    return fail(TACAW_ERR_UNSUPPORTED, "seg_len must be a power of two in [64, 1024] or 200");
+  if (!is_pow2(d->seg_len) && d->transform != TACAW_FFT_F32)
+    return fail(TACAW_ERR_UNSUPPORTED, "seg_len 200 needs the FFT transform");
   if (d->hop < 1 || d->hop > d->seg_len)
     return fail(TACAW_ERR_INVALID_ARG, "hop must satisfy 1 <= hop <= seg_len");
   if (d->n_frames < d->seg_len)
@@ -411,7 +414,7 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   }
   if (d->n_det > 0) {
     A((void**)&P->masks, (int64_t)d->n_det * nk * 8, "masks");
-    A((void**)&P->tile_slot, (int64_t)P->n_tiles * 4, "tile slots");
+    A((void**)&P->pair_slot, (int64_t)P->n_tiles * d->n_det * 4, "detector tile slots");
     A((void**)&P->Dp, (int64_t)d->n_det * np * P->n_om * 8, "per-probe detector spectra");
   }
   if (rc != TACAW_OK) {
@@ -449,20 +452,24 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
     std::vector<double> hm((size_t)d->n_det * nk);
     if (rc == TACAW_OK)
       rc = hip_check(hipMemcpy(hm.data(), P->masks, hm.size() * 8, hipMemcpyDeviceToHost), "mask read");
-    std::vector<int32_t> slots(P->n_tiles, -1);
+    // one partial slot per (tile, detector) whose mask is non-zero on the tile,
+    // numbered detector by detector so each detector's slots are contiguous
+    std::vector<int32_t> slots((size_t)P->n_tiles * d->n_det, -1);
     int act = 0;
-    for (int t = 0; t < P->n_tiles; ++t) {
-      bool any = false;
-      for (int dd = 0; dd < d->n_det && !any; ++dd)
-        for (int64_t k = (int64_t)t * P->W; k < std::min<int64_t>(nk, (int64_t)(t + 1) * P->W); ++k)
+    for (int dd = 0; dd < d->n_det; ++dd) {
+      P->det_slots.off[dd] = act;
+      for (int t = 0; t < P->n_tiles; ++t) {
+        const int64_t k1 = std::min<int64_t>(nk, (int64_t)(t + 1) * P->W);
+        for (int64_t k = (int64_t)t * P->W; k < k1; ++k)
           if (hm[(size_t)dd * nk + k] != 0.0) {
-            any = true;
+            slots[(size_t)t * d->n_det + dd] = act++;
             break;
           }
-      if (any) slots[t] = act++;
+      }
     }
-    P->n_active = act;
-    H2D(P->tile_slot, slots.data(), (int64_t)P->n_tiles * 4);
+    P->det_slots.off[d->n_det] = act;
+    P->n_pairs = act;
+    H2D(P->pair_slot, slots.data(), (int64_t)slots.size() * 4);
   }
   if (rc == TACAW_OK && (d->flags & TACAW_FLAG_TIME_KERNELS)) {
     rc = hip_check(hipEventCreate(&P->ev0), "event");
@@ -580,7 +587,7 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
   }
   int64_t dpart_need = 0;
   if (P->d.n_det > 0 && s_hi > s_lo)
-    dpart_need = (int64_t)std::max(P->n_active, 1) * n_probes * P->d.n_det * P->n_om * 8;
+    dpart_need = (int64_t)std::max(P->n_pairs, 1) * n_probes * P->n_om * 8;
   if (dpart_need > P->dpart_bytes) {
     P->release((void**)&P->dpart);
     P->dpart_bytes = 0;
@@ -632,7 +639,7 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
     g.roi_half = P->roi;
     g.n_det = P->d.n_det;
     g.masks = P->masks;
-    g.tile_slot = P->tile_slot;
+    g.pair_slot = P->pair_slot;
     g.dpart = P->dpart;
     g.gscale = P->gscale;
     const bool sub64 = P->d.in_dtype == TACAW_C128 || P->strategy == kRefExactMean;
@@ -649,8 +656,8 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
       TRY(hip_check(hipEventRecord(P->ev1, P->st), "event"));
       P->timed = true;
     }
-    if (P->d.n_det > 0 && P->n_active > 0)
-      TRY(hip_check(launch_dpart_reduce(P->dpart, P->n_active, n_probes, P->d.n_det, P->n_om, probe0,
+    if (P->d.n_det > 0 && P->n_pairs > 0)
+      TRY(hip_check(launch_dpart_reduce(P->dpart, P->det_slots, n_probes, P->d.n_det, P->n_om, probe0,
                                         P->d.n_probe, P->Dp, P->st),
                     "detector partial reduce"));
   }
@@ -760,6 +767,7 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   if (n_probes > 1 && pstride < 1) return fail(TACAW_ERR_INVALID_ARG, "probe_stride must be >= 1");
   if (P->H != P->L && 2 * P->H != P->L)
     return fail(TACAW_ERR_UNSUPPORTED, "backward supports hop = L or hop = L/2");
+  if (!is_pow2(P->L)) return fail(TACAW_ERR_UNSUPPORTED, "backward needs a power-of-two seg_len");
   if ((gD || gDp) && P->d.n_det == 0)
     return fail(TACAW_ERR_INVALID_ARG, "detector gradients need plan masks");
   int n1b = 0, n2b = 0;

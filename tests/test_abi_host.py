@@ -44,6 +44,7 @@ def _ok(**over):
     (dict(hop=129), "INVALID_ARG"),
     (dict(n_frames=100), "INVALID_ARG"),
     (dict(seg_len=100), "UNSUPPORTED"),
+    (dict(seg_len=200, hop=100, n_frames=400, transform="gemm_bf16x3"), "UNSUPPORTED"),
     (dict(seg_len=2048, n_frames=4096), "UNSUPPORTED"),
     (dict(n_probe=0), "INVALID_ARG"),
     (dict(ny=0), "INVALID_ARG"),
@@ -80,6 +81,7 @@ def test_valid_descriptors_pass():
     tacaw.check_desc(**_ok(window=np.hanning(128), temperature_K=300.0))
     tacaw.check_desc(**_ok(transform="gemm_bf16x3"))
     tacaw.check_desc(**_ok(omega_half=63))
+    tacaw.check_desc(**_ok(seg_len=200, hop=100, n_frames=3200, dt_fs=15.0, omega_half=90))
     tacaw.check_desc(**_ok(omega_half=1, transform="gemm_f16x3", temperature_K=50.0))
 
 

@@ -72,6 +72,7 @@ def check(g, o, tol, label):
     (128, 64, 640, 37, 29, 3, 1),      # narrowest window: the correction bins only
     (256, 128, 700, 16, 20, 2, 127),   # widest window: all bins but the Nyquist bin
     (1024, 512, 2048, 5, 20, 1, 200),
+    (200, 100, 3200, 6, 7, 1, 90),     # the 181 bins of +-30 THz at L = 200, 15 fs
 ])
 def test_fft_window_rows_equal_full_plan_and_oracle(tacaw, L, H, NT, ny, nx, P, M):
     spec = T.SeriesSpec(P, NT, ny, nx, dtype="c64", seed=L + M, model="lines", n_terms=8,

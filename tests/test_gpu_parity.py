@@ -105,6 +105,10 @@ def test_plain_one_probe_complex128(tacaw):
     (512, 512, 1100, 9, 9, 1),     # no overlap, dropped tail
     (1024, 512, 2048, 5, 20, 1),
     (256, 100, 900, 11, 11, 2),    # hop not dividing L: chunk reload path
+    (200, 100, 3200, 6, 7, 1),     # Sec. III.A worked example: L = 200, nu = 2, 31 chunks
+    (200, 100, 700, 9, 13, 2),     # prime-factor 10-point passes, ragged tiles of 32
+    (200, 200, 650, 5, 5, 2),      # no overlap, dropped tail
+    (200, 64, 600, 7, 7, 1),       # general hop
 ])
 def test_lines_model_multi_probe(tacaw, L, H, NT, ny, nx, P):
     spec = T.SeriesSpec(P, NT, ny, nx, dtype="c64", seed=L + H, model="lines", n_terms=8,
@@ -282,3 +286,54 @@ def test_quantum_statistics_factor(tacaw, T_K):
     o = {"S": S, "D": O.detector_spectra(S, masks),
          "Dp": np.transpose(O.detector_spectra(Sp, masks), (1, 0, 2))}
     check(g, o, label=f"quantum factor T={T_K}")
+
+
+def test_seg_len_200_streamed_through_the_ring(tacaw):
+    # L = 200 pieces that straddle chunk boundaries: ring slots indexed by frame mod 200
+    spec = T.SeriesSpec(3, 900, 8, 9, dtype="c64", seed=200, model="lines", n_terms=8)
+    psi = T.generate(spec)
+    masks = T.standard_masks(8, 9, scale=0.06)
+    ref = run_gpu(tacaw, psi, 200, 100, masks)
+    g = run_gpu(tacaw, psi, 200, 100, masks, pushes=[37, 163, 250, 1, 449],
+                probe_batches=[(0, 2), (2, 3)], max_probes_in_flight=2)
+    assert rel(g["S"], ref["S"]) < 1e-12 and rel(g["Dp"], ref["Dp"]) < 1e-12
+    check(g, oracle_all(psi, 200, 100, masks=masks), label="L=200 streamed")
+    assert g["info"]["n_segments"] == O.segment_count(900, 200, 100)
+
+
+def test_seg_len_200_rejects_gemm_and_backward(tacaw):
+    with pytest.raises(tacaw.TacawError) as e:
+        tacaw.Plan(1, 4, 4, 400, 200, 100, transform="gemm_f16x3")
+    assert e.value.kind == "UNSUPPORTED"
+    psi = torch.ones((1, 400, 4, 4), dtype=torch.complex64, device="cuda")
+    plan = tacaw.Plan(1, 4, 4, 400, 200, 100)
+    plan.push(psi)
+    plan.finalize()
+    with pytest.raises(tacaw.TacawError) as e:
+        plan.backward(psi, gS=torch.zeros((200, 4, 4), dtype=torch.float64, device="cuda"))
+    assert e.value.kind == "UNSUPPORTED"
+    plan.close()
+
+
+@pytest.mark.parametrize("window", ["hann", "blackmanharris"])
+def test_leakage_tails_pointwise(tacaw, window):
+    # App. A compares windows by their leakage; the FP32 path must reproduce the
+    # tails bin by bin, not only in the L2 norm: tones half-way between bins on an
+    # elastic background, bins 4.5 .. 32.5 away from each tone
+    import scipy.signal
+
+    L, ny, nx = 512, 4, 8
+    t = np.arange(L)
+    nu = 40.5 + 13.0 * np.arange(ny * nx)  # one tone per pixel, all off-bin
+    x = 1.0 + 1e-3 * np.exp(2j * np.pi * np.outer(t, nu) / L)
+    psi = torch.from_numpy(x.astype(np.complex64).reshape(1, L, ny, nx))
+    w = O.window("hann", L) if window == "hann" else scipy.signal.get_window(window, L)
+    g = run_gpu(tacaw, psi, L, L, window=window if window == "hann" else w)
+    So, _ = O.tacaw_spectra(psi.numpy(), L, L, w)
+    worst = 0.0
+    for k in range(ny * nx):
+        for d in np.arange(4.5, 33.0, 1.0):
+            m = int(nu[k] + d) % L
+            worst = max(worst, abs(g["S"][m, k] - So[m, k]) / So[m, k])
+    say(f"{window} tails: worst pointwise rel err {worst:.2e}")
+    assert worst <= 1e-2

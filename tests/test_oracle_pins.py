@@ -189,6 +189,27 @@ def test_off_bin_tone_hann_closed_form():
     assert int(np.argmax(P)) == round(nu0)
 
 
+def test_leakage_tails_hann_cubic_rect_linear():
+    # Sec. III.A: the Hann window's leakage falls off as 1/omega^3 in amplitude, the
+    # rectangular window's as 1/omega. A tone half-way between bins puts every other
+    # bin in the tail; the log-log slope of |X| over 8.5 .. 32.5 bins away is -3 / -1.
+    L, nu0 = 512, 100.5
+    t = np.arange(L)
+    psi = np.exp(2j * np.pi * nu0 * t / L)[:, None]
+    d = np.array([8.5, 16.5, 32.5])
+    m = (nu0 + d).astype(int)
+    for kind, slope in (("hann", -3.0), ("rect", -1.0)):
+        P = O.segment_spectra(psi, L, L, O.window(kind, L), "none")[0][:, 0]
+        amp = np.sqrt(P[m])
+        fit = np.polyfit(np.log(d), np.log(amp), 1)[0]
+        assert abs(fit - slope) < 0.1, (kind, fit)
+    # Hann: |X(delta)| ~ |sin(pi delta)| / (2 pi delta (delta^2 - 1)) for delta << L
+    P = O.segment_spectra(psi, L, L, O.window("hann", L), "none")[0][:, 0]
+    ref = (1.0 / (2 * np.pi * d * (d ** 2 - 1))) ** 2
+    r = P[m] / ref
+    assert np.ptp(r) / r.mean() < 0.03
+
+
 def test_static_wave_gives_exact_zero():
     # mean subtraction must remove a time-independent wave exactly (S == 0)
     vals = (RNG.standard_normal(6) + 1j * RNG.standard_normal(6)).astype(np.complex64)
