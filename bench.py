@@ -98,6 +98,9 @@ def main():
                          "--probes (default 16) x 4096 frames x 1024^2 c64, L=1024 H=512, "
                          "pushed in pieces of --push-frames frames through the plan's ring")
     ap.add_argument("--push-frames", type=int, default=256)
+    ap.add_argument("--ring-frames", type=int, default=0,
+                    help="streaming: deferred ring depth per probe (0: chunks run in the push "
+                         "that completes them)")
     ap.add_argument("--resident-frames", type=int, default=512,
                     help="streaming: frames held in HBM per probe; pushes cycle through them "
                          "(4096 = the whole series)")
@@ -172,7 +175,7 @@ def main():
     M = axes.omega_half_for(L, dt_fs, e_max_mev=args.roi_mev) if args.roi_mev > 0 else 0
     plan = tacaw.Plan(spec.n_probe, spec.ny, spec.nx, spec.n_frames, L, H, masks=masks,
                       transform=args.form, in_dtype=spec.dtype, time_kernels=True, stream=stream,
-                      dt_fs=dt_fs, omega_half=M)
+                      dt_fs=dt_fs, omega_half=M, ring_frames=args.ring_frames if streaming else 0)
     R = psi.shape[1]
     pieces = [(f0, min(spec.n_frames, f0 + args.push_frames))
               for f0 in range(0, spec.n_frames, args.push_frames)] if streaming else [(0, spec.n_frames)]
@@ -242,6 +245,7 @@ def main():
                         f"Welch L={L} H={H} periodic Hann, global mean, {masks.shape[0]} detector masks, "
                         f"transform {args.form}"
                         + (f", pushed in pieces of {args.push_frames} frames" if streaming else "")
+                        + (f", deferred ring of {args.ring_frames} frames" if streaming and args.ring_frames else "")
                         + (f", energy window |E| <= {args.roi_mev:g} meV ({n_om} bins)" if M else ""),
             "probes": spec.n_probe, "frames": spec.n_frames, "ny": spec.ny, "nx": spec.nx,
             "seg_len": L, "hop": H, "n_omega": n_om, "exit_wave_bytes": b_alg,

@@ -104,6 +104,14 @@ typedef struct {
                           /* 0: no factor                                            */
   const double* h_window; /* host array of seg_len window values (TACAW_WIN_CUSTOM)  */
                           /* copied at plan creation; NULL otherwise                 */
+  int64_t ring_frames;    /* streaming ring depth D per in-flight probe: 0 = seg_len,*/
+                          /* chunks are processed by the push that completes them;   */
+                          /* D > seg_len (a multiple of 64; D - seg_len >= every     */
+                          /* push) = deferred mode: pushes are copied into the ring  */
+                          /* and completed chunks are processed from it in batches,  */
+                          /* when the ring would overwrite them and at the end of    */
+                          /* each probe's series (fewer, larger launches; FFT form,  */
+                          /* compact windows)                                        */
   int32_t omega_half;     /* energy window (the centred +-ROI of Sec. II.B / App. B):*/
                           /* 0 = all seg_len bins in FFT order; M in [1, L/2 - 1] =  */
                           /* only the 2M + 1 bins of signed index -M..M (frequency   */

@@ -89,34 +89,41 @@ hipError_t launch_ref_mean(const void* in, int in_dtype, int64_t pstride, int64_
                            st);
 }
 
-// ring[slot][f % L][k] = in[i][f - push_begin][k] for f in [f_lo, f_hi)
+// ring[slot][f % D][k] = in[i][f - push_begin][k] for f in [f_lo, f_hi); each
+// thread copies 16 bytes (two complex64 or one complex128 element)
 template <typename InT>
 __global__ void ring_store_kernel(const InT* in, int64_t pstride, int64_t fstride,
                                   int64_t push_begin, int64_t f_lo, int32_t n_f, int32_t probe0,
-                                  int32_t n_slots, int32_t L, int32_t n_k, InT* ring) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                  int32_t n_slots, int64_t depth, int32_t n_k, InT* ring) {
+  constexpr int V = 16 / (int)sizeof(InT);  // elements per thread
+  const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V;
   const int fi = blockIdx.y;
   const int i = blockIdx.z;
-  if (k >= n_k || fi >= n_f) return;
+  if (k0 >= n_k || fi >= n_f) return;
   const int64_t f = f_lo + fi;
   const int slot = (probe0 + i) % n_slots;
-  ring[((int64_t)slot * L + (f % L)) * n_k + k] = in[(int64_t)i * pstride + (f - push_begin) * fstride + k];
+  InT* dst = ring + ((int64_t)slot * depth + (f % depth)) * n_k;
+  const InT* src = in + (int64_t)i * pstride + (f - push_begin) * fstride;
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+    if (k0 + v < n_k) dst[k0 + v] = src[k0 + v];
 }
 
 hipError_t launch_ring_store(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
                              int64_t push_begin, int64_t f_lo, int64_t f_hi, int32_t probe0,
-                             int32_t n_probes, int32_t n_slots, int32_t L, int32_t n_k, void* ring,
-                             hipStream_t st) {
+                             int32_t n_probes, int32_t n_slots, int64_t depth, int32_t n_k,
+                             void* ring, hipStream_t st) {
   const int64_t nf = f_hi - f_lo;
   if (nf <= 0) return hipSuccess;
-  dim3 g((n_k + 255) / 256, (unsigned)nf, n_probes);
+  const int V = in_dtype == 1 ? 1 : 2;
+  dim3 g((unsigned)((n_k + 256 * V - 1) / (256 * V)), (unsigned)nf, n_probes);
   if (in_dtype == 1)
     hipLaunchKernelGGL(ring_store_kernel<double2>, g, dim3(256), 0, st, (const double2*)in,
-                       pstride, fstride, push_begin, f_lo, (int32_t)nf, probe0, n_slots, L, n_k,
-                       (double2*)ring);
+                       pstride, fstride, push_begin, f_lo, (int32_t)nf, probe0, n_slots, depth,
+                       n_k, (double2*)ring);
   else
     hipLaunchKernelGGL(ring_store_kernel<float2>, g, dim3(256), 0, st, (const float2*)in, pstride,
-                       fstride, push_begin, f_lo, (int32_t)nf, probe0, n_slots, L, n_k,
+                       fstride, push_begin, f_lo, (int32_t)nf, probe0, n_slots, depth, n_k,
                        (float2*)ring);
   return hipGetLastError();
 }

@@ -187,8 +187,18 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
   // LEAN: raw samples of the next chunk, loaded one chunk ahead (software prefetch)
   InT pre[LEAN ? N1 : 1];
   auto fetch_at = [&](int ii, int ss, int n1) -> InT {
-    const char* rb = (const char*)a.in + (int64_t)ii * a.pstride * ESZ +
-                     ((int64_t)ss * H - a.push_begin + N2 * n1) * row_bytes;
+    const char* rb;
+    if (a.from_ring) {
+      // ring rows (ss H + N2 n1) mod D of probe probe0 + ii; D and H are multiples of
+      // N2, so a row group never wraps (row_bytes is one frame of the ring here)
+      int64_t row = ((int64_t)ss * H) % a.ring_depth + N2 * n1;
+      if (row >= a.ring_depth) row -= a.ring_depth;
+      const int64_t slot = (a.probe0 + ii) % a.n_slots;
+      rb = (const char*)a.ring + (slot * a.ring_depth + row) * row_bytes;
+    } else {
+      rb = (const char*)a.in + (int64_t)ii * a.pstride * ESZ +
+           ((int64_t)ss * H - a.push_begin + N2 * n1) * row_bytes;
+    }
     return buffer_load<InT>(rb, group_bytes, lane_off);
   };
   if constexpr (LEAN) {
@@ -203,7 +213,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
     const float2 cf = make_float2((float)cr.x, (float)cr.y);
     const char* in_probe = (const char*)a.in + (int64_t)i * a.pstride * ESZ;
     const InT* ringb =
-        a.ring ? (const InT*)a.ring + ((int64_t)(p % a.n_slots) * L) * n_k + kc : nullptr;
+        a.ring ? (const InT*)a.ring + ((int64_t)(p % a.n_slots) * a.ring_depth) * n_k + kc : nullptr;
     double2 msum = make_double2(0.0, 0.0);
     double2 xsum = make_double2(0.0, 0.0);
     float2 kept[HALF];
@@ -252,7 +262,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
         const int64_t f = seg0 + N2 * n1 + n2;
         if (f >= a.push_begin)
           return *(const InT*)(in_probe + (f - a.push_begin) * row_bytes + kc * ESZ);
-        return ringb[(f % L) * (int64_t)n_k];
+        return ringb[(f % a.ring_depth) * (int64_t)n_k];
       };
       auto load_range = [&](int lo, auto fetch, auto cmode) {
 #pragma unroll
@@ -481,7 +491,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
 template <int L, typename InT, bool SUB64>
 static hipError_t launch_t(const SegArgs& a, int n_tiles, hipStream_t st) {
   constexpr int NT = FftShape<L>::W * (L / FftShape<L>::N1);
-  const bool lean = (2 * a.hop == L) && ((int64_t)a.s_lo * a.hop >= a.push_begin);
+  const bool lean = (2 * a.hop == L) && (a.from_ring || (int64_t)a.s_lo * a.hop >= a.push_begin);
   if (lean) {
     if (a.n_det > 0)
       hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, true>), dim3(n_tiles), dim3(NT), 0, st, a);

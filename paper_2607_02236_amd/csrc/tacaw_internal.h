@@ -16,7 +16,10 @@ struct SegArgs {
   int64_t pstride;         // elements
   int64_t fstride;         // elements
   int64_t push_begin;      // absolute frame index of the push buffer's frame 0
-  const void* ring;        // [n_slots][L][n_k] frames pushed earlier, slot = probe % n_slots
+  const void* ring;        // [n_slots][D][n_k] frames pushed earlier, slot = probe % n_slots,
+                           // frame f at row f mod D
+  int64_t ring_depth;      // D (>= L)
+  int32_t from_ring;       // whole-series variant: every chunk is read from the ring
   int32_t n_slots;
   int32_t n_k;
   int32_t probe0;          // first probe of the push
@@ -67,7 +70,7 @@ hipError_t launch_ref_mean(const void* in, int in_dtype, int64_t pstride, int64_
                            double2* cref, hipStream_t st);
 hipError_t launch_ring_store(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
                              int64_t push_begin, int64_t f_lo, int64_t f_hi, int32_t probe0,
-                             int32_t n_probes, int32_t n_slots, int32_t L, int32_t n_k,
+                             int32_t n_probes, int32_t n_slots, int64_t depth, int32_t n_k,
                              void* ring, hipStream_t st);
 // det_off[d] .. det_off[d + 1]: the dpart slots of detector d (n_det + 1 entries)
 struct DetSlots {

@@ -26,6 +26,7 @@ int fail(int code, const std::string& msg) {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr int64_t kMaxDeviceBytes = (int64_t)260 << 30;  // refuse plans beyond HBM capacity
+constexpr int kMaxTimed = 2;  // chunk launches per push (deferred mode: before and after the store)
 
 enum MeanStrategy {
   kRefFirstFrame = 0,  // c = frame 0, exact correction at finalize (compact windows)
@@ -193,8 +194,11 @@ struct tacaw_plan_s {
   int64_t scratch_bytes = 0;
   float* gscale = nullptr;  // GEMM form: [P][n_k]
   double* qfac = nullptr;   // [n_om] quantum-statistics factor per row (temperature > 0)
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  bool timed = false;
+  hipEvent_t ev[kMaxTimed][2] = {};  // chunk-kernel timing, up to kMaxTimed launches per push
+  int n_timed = 0;                    // launches timed in the last push
+  int64_t D = 0;                      // ring depth (frames per slot)
+  bool deferred = false;              // deferred ring mode (ring_frames > seg_len)
+  std::vector<int> s_done;            // deferred mode: chunks processed per probe
 
   int alloc(void** p, int64_t bytes, const char* what) {
     if (bytes <= 0) {
@@ -227,8 +231,9 @@ struct tacaw_plan_s {
     (void)hipStreamSynchronize(st);
     for (auto& o : owned)
       if (*o.first) (void)hipFree(*o.first);
-    if (ev0) (void)hipEventDestroy(ev0);
-    if (ev1) (void)hipEventDestroy(ev1);
+    for (auto& e : ev)
+      for (auto& x : e)
+        if (x) (void)hipEventDestroy(x);
   }
 };
 
@@ -247,6 +252,65 @@ static int hip_check(hipError_t e, const char* what) {
   } while (0)
 
 static bool transform_is_gemm(int t) { return t == TACAW_GEMM_BF16X3 || t == TACAW_GEMM_F16X3; }
+
+// One chunk-kernel launch over chunks [s_lo, s_hi) of probes [probe0, probe0 + n_probes),
+// followed by the per-probe detector partial reduce. from_ring: every frame is read from
+// the ring (deferred mode); otherwise from the push buffer `src` (frame push_begin at its
+// row 0) and, for frames before push_begin, from the ring.
+static int run_chunks(tacaw_plan_t P, const void* src, int64_t pstride, int64_t fstride,
+                      int64_t push_begin, bool from_ring, int probe0, int n_probes, int s_lo,
+                      int s_hi) {
+  SegArgs g{};
+  g.in = src;
+  g.pstride = pstride;
+  g.fstride = fstride;
+  g.push_begin = from_ring ? ((int64_t)1 << 62) : push_begin;
+  g.ring = P->ring;
+  g.ring_depth = P->D;
+  g.from_ring = from_ring ? 1 : 0;
+  g.n_slots = P->n_slots;
+  g.n_k = P->n_k;
+  g.probe0 = probe0;
+  g.n_probes = n_probes;
+  g.s_lo = s_lo;
+  g.s_hi = s_hi;
+  g.hop = P->H;
+  g.track_mean = P->strategy == kRefFirstFrame ? 1 : 0;
+  g.n_corr = P->n_corr;
+  g.win_t = P->win_t;
+  g.tw = P->tw;
+  g.cref = P->cref;
+  g.msum = P->msum;
+  g.xs = P->xs;
+  g.S = P->S;
+  g.n_om = P->n_om;
+  g.roi_half = P->roi;
+  g.n_det = P->d.n_det;
+  g.masks = P->masks;
+  g.pair_slot = P->pair_slot;
+  g.dpart = P->dpart;
+  g.gscale = P->gscale;
+  const bool sub64 = P->d.in_dtype == TACAW_C128 || P->strategy == kRefExactMean;
+  const bool timed = P->n_timed < kMaxTimed && P->ev[0][0];
+  if (timed) TRY(hip_check(hipEventRecord(P->ev[P->n_timed][0], P->st), "event"));
+  if (transform_is_gemm(P->d.transform))
+    TRY(hip_check(launch_seg_gemm(P->L, P->d.in_dtype, sub64,
+                                  P->d.transform == TACAW_GEMM_F16X3 ? 1 : 0, g, P->fmat,
+                                  P->m_rows, P->n_tiles, P->st),
+                  "chunk GEMM kernel"));
+  else
+    TRY(hip_check(launch_seg_fft(P->L, P->d.in_dtype, sub64, g, P->n_tiles, P->st),
+                  "chunk FFT kernel"));
+  if (timed) {
+    TRY(hip_check(hipEventRecord(P->ev[P->n_timed][1], P->st), "event"));
+    ++P->n_timed;
+  }
+  if (P->d.n_det > 0 && P->n_pairs > 0)
+    TRY(hip_check(launch_dpart_reduce(P->dpart, P->det_slots, n_probes, P->d.n_det, P->n_om,
+                                      probe0, P->d.n_probe, P->Dp, P->st),
+                  "detector partial reduce"));
+  return TACAW_OK;
+}
 
 extern "C" {
 
@@ -296,6 +360,13 @@ int tacaw_plan_check(const tacaw_plan_desc* d) {
     return fail(TACAW_ERR_INVALID_ARG, "max_probes_in_flight must be in [0, n_probe]");
   if (d->omega_half < 0 || d->omega_half > d->seg_len / 2 - 1)
     return fail(TACAW_ERR_INVALID_ARG, "omega_half must be in [0, seg_len/2 - 1]");
+  if (d->ring_frames != 0) {
+    if (d->ring_frames <= d->seg_len || d->ring_frames % (d->seg_len / 2) != 0)
+      return fail(TACAW_ERR_INVALID_ARG,
+                  "ring_frames must be 0 or a multiple of seg_len/2 larger than seg_len");
+    if (d->transform != TACAW_FFT_F32)
+      return fail(TACAW_ERR_UNSUPPORTED, "deferred ring mode needs the FFT transform");
+  }
   const int64_t n_k = (int64_t)d->ny * d->nx;
   const int64_t n_om = d->omega_half > 0 ? 2 * (int64_t)d->omega_half + 1 : d->seg_len;
   const int64_t need = n_om * n_k * 8 + (int64_t)d->n_probe * n_k * 80 +
@@ -325,6 +396,9 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   P->W = gemm ? seg_gemm_tile_pixels(P->L) : seg_fft_tile_pixels(P->L);
   P->n_tiles = (P->n_k + P->W - 1) / P->W;
   P->cursor.assign(d->n_probe, 0);
+  P->s_done.assign(d->n_probe, 0);
+  P->deferred = d->ring_frames > 0;
+  P->D = P->deferred ? d->ring_frames : P->L;
   P->n_slots = d->max_probes_in_flight > 0 ? d->max_probes_in_flight : d->n_probe;
   P->slot_owner.assign(P->n_slots, -1);
 
@@ -371,6 +445,11 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   else
     P->strategy = d->mean_mode == TACAW_MEAN_GLOBAL ? kRefExactMean : kRefZero;
 
+  if (P->deferred && P->strategy != kRefFirstFrame) {
+    delete P;
+    return fail(TACAW_ERR_UNSUPPORTED,
+                "deferred ring mode needs a window whose DFT is confined to bins 0 and +-1");
+  }
   // FFT split L = N1 * N2 (tables are laid out per pass-1 thread)
   seg_fft_split(P->L, &P->N1, &P->N2);
   std::vector<float> wt(P->L), dwt(P->L);
@@ -472,8 +551,9 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
     H2D(P->pair_slot, slots.data(), (int64_t)slots.size() * 4);
   }
   if (rc == TACAW_OK && (d->flags & TACAW_FLAG_TIME_KERNELS)) {
-    rc = hip_check(hipEventCreate(&P->ev0), "event");
-    if (rc == TACAW_OK) rc = hip_check(hipEventCreate(&P->ev1), "event");
+    for (auto& e : P->ev)
+      for (auto& x : e)
+        if (rc == TACAW_OK) rc = hip_check(hipEventCreate(&x), "event");
   }
   if (rc == TACAW_OK) rc = hip_check(hipDeviceSynchronize(), "plan setup");
   if (rc == TACAW_OK) {
@@ -499,6 +579,7 @@ int tacaw_reset(tacaw_plan_t P) {
   if (P->Dp)
     TRY(hip_check(launch_fill_zero(P->Dp, (int64_t)P->d.n_det * np * P->n_om * 8, P->st), "reset"));
   std::fill(P->cursor.begin(), P->cursor.end(), 0);
+  std::fill(P->s_done.begin(), P->s_done.end(), 0);
   std::fill(P->slot_owner.begin(), P->slot_owner.end(), -1);
   P->state = 0;
   P->dropped = 0;
@@ -526,10 +607,17 @@ int tacaw_plan_get_info(tacaw_plan_t P, tacaw_plan_info* info) {
   info->window_sum_sq = P->sumw2;
   info->tile_pixels = P->W;
   info->last_chunk_kernel_ms = -1.0;
-  if (P->timed && P->ev1) {
-    float ms = 0.0f;
-    if (hipEventSynchronize(P->ev1) == hipSuccess && hipEventElapsedTime(&ms, P->ev0, P->ev1) == hipSuccess)
-      info->last_chunk_kernel_ms = ms;
+  if (P->n_timed > 0) {
+    double tot = 0.0;
+    bool ok = true;
+    for (int i = 0; i < P->n_timed && ok; ++i) {
+      float ms = 0.0f;
+      ok = hipEventSynchronize(P->ev[i][1]) == hipSuccess &&
+           hipEventElapsedTime(&ms, P->ev[i][0], P->ev[i][1]) == hipSuccess;
+      tot += ms;
+    }
+    if (ok)
+      info->last_chunk_kernel_ms = tot;
     else
       (void)hipGetLastError();
   }
@@ -567,11 +655,18 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
 
   const int s_lo = (int)std::min<int64_t>(P->Ns, seg_count(a, P->L, P->H));
   const int s_hi = (int)std::min<int64_t>(P->Ns, seg_count(b, P->L, P->H));
-  // frames later chunks still need after this push
+  if (P->deferred) {
+    if (n_frames > P->D - P->L)
+      return fail(TACAW_ERR_SHAPE, "in deferred mode a push may hold at most ring_frames - seg_len frames");
+    for (int i = 1; i < n_probes; ++i)
+      if (P->s_done[probe0 + i] != P->s_done[probe0])
+        return fail(TACAW_ERR_STATE, "probes of one push must have processed the same chunks");
+  }
+  // frames later chunks still need after this push (immediate mode)
   const int64_t keep_lo = std::max<int64_t>(a, (int64_t)s_hi * P->H);
   const int64_t keep_hi = std::min<int64_t>(b, P->n_used);
-  const bool need_ring_write = s_hi < P->Ns && keep_hi > keep_lo;
-  const bool need_ring_read = s_hi > s_lo && (int64_t)s_lo * P->H < a;
+  const bool need_ring_write = P->deferred ? a < P->n_used : (s_hi < P->Ns && keep_hi > keep_lo);
+  const bool need_ring_read = P->deferred || (s_hi > s_lo && (int64_t)s_lo * P->H < a);
   if (need_ring_write || need_ring_read) {
     if (n_probes > P->n_slots)
       return fail(TACAW_ERR_STATE, "ring capacity exceeded: more probes in flight than ring slots");
@@ -581,18 +676,18 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
         return fail(TACAW_ERR_STATE, "ring capacity exceeded: too many probes in flight");
     }
     if (!P->ring) {
-      const int64_t rb = (int64_t)P->n_slots * P->L * P->n_k * P->esz;
+      const int64_t rb = (int64_t)P->n_slots * P->D * P->n_k * P->esz;
       TRY(P->alloc(&P->ring, rb, "frame ring"));
     }
   }
-  int64_t dpart_need = 0;
-  if (P->d.n_det > 0 && s_hi > s_lo)
-    dpart_need = (int64_t)std::max(P->n_pairs, 1) * n_probes * P->n_om * 8;
-  if (dpart_need > P->dpart_bytes) {
-    P->release((void**)&P->dpart);
-    P->dpart_bytes = 0;
-    TRY(P->alloc((void**)&P->dpart, dpart_need, "detector partials"));
-    P->dpart_bytes = dpart_need;
+  if (P->d.n_det > 0) {
+    const int64_t dpart_need = (int64_t)std::max(P->n_pairs, 1) * n_probes * P->n_om * 8;
+    if (dpart_need > P->dpart_bytes) {
+      P->release((void**)&P->dpart);
+      P->dpart_bytes = 0;
+      TRY(P->alloc((void**)&P->dpart, dpart_need, "detector partials"));
+      P->dpart_bytes = dpart_need;
+    }
   }
 
   // 1. references at the first frame of each probe
@@ -611,61 +706,33 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
                                       P->cref, P->gscale, P->st),
                     "operand scale pre-pass"));
   }
-  // 2. every chunk completed by this push
-  P->timed = false;
-  if (s_hi > s_lo) {
-    SegArgs g{};
-    g.in = frames;
-    g.pstride = pstride;
-    g.fstride = fstride;
-    g.push_begin = a;
-    g.ring = P->ring;
-    g.n_slots = P->n_slots;
-    g.n_k = P->n_k;
-    g.probe0 = probe0;
-    g.n_probes = n_probes;
-    g.s_lo = s_lo;
-    g.s_hi = s_hi;
-    g.hop = P->H;
-    g.track_mean = P->strategy == kRefFirstFrame ? 1 : 0;
-    g.n_corr = P->n_corr;
-    g.win_t = P->win_t;
-    g.tw = P->tw;
-    g.cref = P->cref;
-    g.msum = P->msum;
-    g.xs = P->xs;
-    g.S = P->S;
-    g.n_om = P->n_om;
-    g.roi_half = P->roi;
-    g.n_det = P->d.n_det;
-    g.masks = P->masks;
-    g.pair_slot = P->pair_slot;
-    g.dpart = P->dpart;
-    g.gscale = P->gscale;
-    const bool sub64 = P->d.in_dtype == TACAW_C128 || P->strategy == kRefExactMean;
-    if (P->ev0) TRY(hip_check(hipEventRecord(P->ev0, P->st), "event"));
-    if (transform_is_gemm(P->d.transform))
-      TRY(hip_check(launch_seg_gemm(P->L, P->d.in_dtype, sub64,
-                                    P->d.transform == TACAW_GEMM_F16X3 ? 1 : 0, g, P->fmat,
-                                    P->m_rows, P->n_tiles, P->st),
-                    "chunk GEMM kernel"));
-    else
-      TRY(hip_check(launch_seg_fft(P->L, P->d.in_dtype, sub64, g, P->n_tiles, P->st),
-                    "chunk FFT kernel"));
-    if (P->ev1) {
-      TRY(hip_check(hipEventRecord(P->ev1, P->st), "event"));
-      P->timed = true;
+  P->n_timed = 0;
+  if (!P->deferred) {
+    // 2. every chunk completed by this push, read from the push (and the ring)
+    if (s_hi > s_lo) TRY(run_chunks(P, frames, pstride, fstride, a, false, probe0, n_probes, s_lo, s_hi));
+    // 3. keep what later chunks need
+    if (need_ring_write)
+      TRY(hip_check(launch_ring_store(frames, P->d.in_dtype, pstride, fstride, a, keep_lo, keep_hi,
+                                      probe0, n_probes, P->n_slots, P->D, P->n_k, P->ring, P->st),
+                    "ring store"));
+  } else {
+    // deferred: completed chunks wait in the ring until this push would overwrite the
+    // oldest of them (then all completed ones run in one launch) or the series ends
+    int sd = P->s_done[probe0];
+    if (sd < s_lo && (int64_t)sd * P->H < b - P->D) {
+      TRY(run_chunks(P, P->ring, 0, P->n_k, 0, true, probe0, n_probes, sd, s_lo));
+      sd = s_lo;
     }
-    if (P->d.n_det > 0 && P->n_pairs > 0)
-      TRY(hip_check(launch_dpart_reduce(P->dpart, P->det_slots, n_probes, P->d.n_det, P->n_om, probe0,
-                                        P->d.n_probe, P->Dp, P->st),
-                    "detector partial reduce"));
-  }
-  // 3. keep what later chunks need
-  if (need_ring_write) {
-    TRY(hip_check(launch_ring_store(frames, P->d.in_dtype, pstride, fstride, a, keep_lo, keep_hi,
-                                    probe0, n_probes, P->n_slots, P->L, P->n_k, P->ring, P->st),
-                  "ring store"));
+    if (need_ring_write)
+      TRY(hip_check(launch_ring_store(frames, P->d.in_dtype, pstride, fstride, a, a,
+                                      std::min<int64_t>(b, P->n_used), probe0, n_probes,
+                                      P->n_slots, P->D, P->n_k, P->ring, P->st),
+                    "ring store"));
+    if (b >= P->n_used && sd < P->Ns) {
+      TRY(run_chunks(P, P->ring, 0, P->n_k, 0, true, probe0, n_probes, sd, P->Ns));
+      sd = P->Ns;
+    }
+    for (int i = 0; i < n_probes; ++i) P->s_done[probe0 + i] = sd;
   }
   for (int i = 0; i < n_probes; ++i) {
     const int p = probe0 + i, sl = p % P->n_slots;

@@ -337,3 +337,35 @@ def test_leakage_tails_pointwise(tacaw, window):
             worst = max(worst, abs(g["S"][m, k] - So[m, k]) / So[m, k])
     say(f"{window} tails: worst pointwise rel err {worst:.2e}")
     assert worst <= 1e-2
+
+
+@pytest.mark.parametrize("L,H,NT,D,pushes", [
+    (128, 64, 640, 192, [64, 1, 63, 64, 64, 40, 24, 64, 64, 64, 64, 64]),  # D = L + 64: every push forces
+    (128, 64, 640, 512, [100, 200, 300, 40]),                               # batches of chunks
+    (128, 64, 640, 704, [512, 128]),                                         # whole series deferred
+    (200, 100, 900, 300, [100] * 9),                                         # L = 200
+    (256, 100, 900, 384, [128] * 7 + [4]),                                   # hop != L/2: general path
+])
+def test_deferred_ring_mode_matches_immediate_and_oracle(tacaw, L, H, NT, D, pushes):
+    spec = T.SeriesSpec(3, NT, 9, 7, dtype="c64", seed=D + L, model="lines", n_terms=8)
+    psi = T.generate(spec)
+    masks = T.standard_masks(9, 7, scale=0.06)
+    masks[3] = np.random.default_rng(12).random((9, 7))
+    ref = run_gpu(tacaw, psi, L, H, masks)
+    g = run_gpu(tacaw, psi, L, H, masks, pushes=pushes, probe_batches=[(0, 2), (2, 3)],
+                max_probes_in_flight=2, ring_frames=D)
+    assert rel(g["S"], ref["S"]) < 1e-12 and rel(g["Dp"], ref["Dp"]) < 1e-12
+    check(g, oracle_all(psi, L, H, masks=masks), label=f"deferred L={L} H={H} D={D}")
+
+
+def test_deferred_ring_mode_errors(tacaw):
+    psi = torch.ones((1, 640, 4, 4), dtype=torch.complex64, device="cuda")
+    plan = tacaw.Plan(1, 4, 4, 640, 128, 64, ring_frames=256)
+    with pytest.raises(tacaw.TacawError) as e:
+        plan.push(psi[:, :129])  # more than ring_frames - seg_len
+    assert e.value.kind == "SHAPE"
+    plan.push(psi[:, :128])
+    plan.close()
+    with pytest.raises(tacaw.TacawError) as e:  # non-compact window: exact-mean pre-pass
+        tacaw.Plan(1, 4, 4, 640, 128, 64, window="tukey", window_param=0.5, ring_frames=256)
+    assert e.value.kind == "UNSUPPORTED"
