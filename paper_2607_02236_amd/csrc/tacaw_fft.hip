@@ -482,7 +482,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
       if (row >= L) row -= L;
       if (row < a.n_om) {
         double* sp = a.S + (int64_t)row * n_k + k;
-        *sp += acc[t];
+        *sp = a.s_store ? acc[t] : *sp + acc[t];
       }
     }
   }

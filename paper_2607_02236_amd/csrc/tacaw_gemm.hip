@@ -236,7 +236,10 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
       for (int q = 0; q < 8; ++q) {
         const int rblk = wave + kGemmWaves * b;
         const int r = 16 * rblk + 4 * (q / 2) + 2 * half + (q % 2);
-        if (r < n_om) a.S[(int64_t)r * n_k + kcol] += acc64[b][q];
+        if (r < n_om) {
+          double* sp = a.S + (int64_t)r * n_k + kcol;
+          *sp = a.s_store ? acc64[b][q] : *sp + acc64[b][q];
+        }
       }
     }
   }

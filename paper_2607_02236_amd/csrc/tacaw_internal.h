@@ -34,6 +34,7 @@ struct SegArgs {
   double2* msum;           // [n_probe][n_k] FP64 sum of (psi - c) over counted frames
   double2* xs;             // [n_probe][kMaxCorr][n_k] FP64 sum over chunks of X'(bin)
   double* S;               // [n_om][n_k] FP64 accumulator of sum |X'|^2
+  int32_t s_store;         // 1: first launch since reset, S is written (not read and added)
   int32_t n_om;            // output rows: L, or 2 roi_half + 1
   int32_t roi_half;        // energy window M (0 = all bins); bin m -> row (m + M) mod L
   int32_t n_det;           // per-probe detector partials (0 = off)

@@ -199,6 +199,7 @@ struct tacaw_plan_s {
   int64_t D = 0;                      // ring depth (frames per slot)
   bool deferred = false;              // deferred ring mode (ring_frames > seg_len)
   std::vector<int> s_done;            // deferred mode: chunks processed per probe
+  bool s_fresh = true;                // no chunk launch since the last reset: S is undefined
 
   int alloc(void** p, int64_t bytes, const char* what) {
     if (bytes <= 0) {
@@ -283,6 +284,8 @@ static int run_chunks(tacaw_plan_t P, const void* src, int64_t pstride, int64_t 
   g.msum = P->msum;
   g.xs = P->xs;
   g.S = P->S;
+  g.s_store = P->s_fresh ? 1 : 0;
+  P->s_fresh = false;
   g.n_om = P->n_om;
   g.roi_half = P->roi;
   g.n_det = P->d.n_det;
@@ -575,11 +578,12 @@ int tacaw_reset(tacaw_plan_t P) {
   TRY(hip_check(launch_fill_zero(P->cref, np * nk * 16, P->st), "reset"));
   TRY(hip_check(launch_fill_zero(P->msum, np * nk * 16, P->st), "reset"));
   TRY(hip_check(launch_fill_zero(P->xs, np * kMaxCorr * nk * 16, P->st), "reset"));
-  TRY(hip_check(launch_fill_zero(P->S, (int64_t)P->n_om * nk * 8, P->st), "reset"));
+  // S needs no zero fill: the first chunk launch after a reset writes every element
   if (P->Dp)
     TRY(hip_check(launch_fill_zero(P->Dp, (int64_t)P->d.n_det * np * P->n_om * 8, P->st), "reset"));
   std::fill(P->cursor.begin(), P->cursor.end(), 0);
   std::fill(P->s_done.begin(), P->s_done.end(), 0);
+  P->s_fresh = true;
   std::fill(P->slot_owner.begin(), P->slot_owner.end(), -1);
   P->state = 0;
   P->dropped = 0;
