@@ -112,6 +112,10 @@ typedef struct {
                           /* when the ring would overwrite them and at the end of    */
                           /* each probe's series (fewer, larger launches; FFT form,  */
                           /* compact windows)                                        */
+  int64_t k_row_stride;   /* k-space window (the k-ROI of Sec. II.B): elements       */
+                          /* between the input's pixel rows, >= nx (0 = nx). The    */
+                          /* ny x nx pixels reduced are then a window of a wider     */
+                          /* grid, read in place by pushes and the adjoint.          */
   int32_t omega_half;     /* energy window (the centred +-ROI of Sec. II.B / App. B):*/
                           /* 0 = all seg_len bins in FFT order; M in [1, L/2 - 1] =  */
                           /* only the 2M + 1 bins of signed index -M..M (frequency   */
@@ -151,9 +155,10 @@ int tacaw_plan_check(const tacaw_plan_desc* desc);
 
 /* Push the next n_frames frames of probes [probe0, probe0 + n_probes) in time
  * order (Sec. II.B: exit waves are processed on the fly as they are produced).
- * Element (i, n, k) of the push, for probe probe0 + i, frame cursor + n and
- * pixel k, is at d_frames + i * probe_stride + n * frame_stride + k, strides in
- * ELEMENTS of in_dtype (pixels contiguous). All probes of one push must have
+ * Element (i, n, ky, kx) of the push, for probe probe0 + i, frame cursor + n and
+ * pixel (ky, kx), is at d_frames + i * probe_stride + n * frame_stride +
+ * ky * R + kx, strides in ELEMENTS of in_dtype, R = k_row_stride (nx if 0), and
+ * frame_stride >= (ny - 1) R + nx. All probes of one push must have
  * received the same number of frames before. Every chunk completed by this push
  * is windowed, transformed, squared and accumulated in FP64; frames that later
  * chunks still need are copied into a plan-owned ring (last L frames per probe

@@ -103,8 +103,9 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
       Gt[t] = (float)g;
     }
     const double2 mu = a.mu ? a.mu[(int64_t)p * n_k + kc] : make_double2(0.0, 0.0);
-    const InT* inp = (const InT*)a.in + (int64_t)i * a.pstride + kc;
-    InT* gp = (InT*)a.grad + (int64_t)i * a.pstride + kc;
+    const int64_t kin = pix_off(kc, a.nx, a.row_stride);
+    const InT* inp = (const InT*)a.in + (int64_t)i * a.pstride + kin;
+    InT* gp = (InT*)a.grad + (int64_t)i * a.pstride + kin;
     float2 carry[HALF];
 #pragma unroll
     for (int u = 0; u < HALF; ++u) carry[u] = make_float2(0.f, 0.f);
@@ -213,7 +214,7 @@ __global__ void bwd_mean_fix_kernel(const BwdArgs a) {
   if (k >= a.n_k) return;
   const double2 g = a.gmean[(int64_t)i * a.n_k + k];
   const double sx = g.x * a.inv_nused, sy = g.y * a.inv_nused;
-  InT* gp = (InT*)a.grad + (int64_t)i * a.pstride + k;
+  InT* gp = (InT*)a.grad + (int64_t)i * a.pstride + pix_off(k, a.nx, a.row_stride);
   for (int64_t n = blockIdx.y; n < a.n_used; n += gridDim.y) {
     InT v = gp[n * a.fstride];
     v.x = (decltype(v.x))((double)v.x - sx);

@@ -31,35 +31,37 @@ hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st) {
 }
 
 template <typename InT>
-__global__ void ref_first_kernel(const InT* in, int64_t pstride, int32_t probe0, int32_t n_probes,
-                                 int32_t n_k, double2* cref) {
+__global__ void ref_first_kernel(const InT* in, int64_t pstride, int32_t nx, int64_t rs,
+                                 int32_t probe0, int32_t n_probes, int32_t n_k, double2* cref) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (k >= n_k || i >= n_probes) return;
-  const InT v = in[(int64_t)i * pstride + k];
+  const InT v = in[(int64_t)i * pstride + pix_off(k, nx, rs)];
   cref[(int64_t)(probe0 + i) * n_k + k] = make_double2((double)v.x, (double)v.y);
 }
 
-hipError_t launch_ref_first_frame(const void* in, int in_dtype, int64_t pstride, int32_t probe0,
-                                  int32_t n_probes, int32_t n_k, double2* cref, hipStream_t st) {
+hipError_t launch_ref_first_frame(const void* in, int in_dtype, int64_t pstride, int32_t nx,
+                                  int64_t rs, int32_t probe0, int32_t n_probes, int32_t n_k,
+                                  double2* cref, hipStream_t st) {
   dim3 g((n_k + 255) / 256, n_probes);
   if (in_dtype == 1)
     hipLaunchKernelGGL(ref_first_kernel<double2>, g, dim3(256), 0, st, (const double2*)in,
-                       pstride, probe0, n_probes, n_k, cref);
+                       pstride, nx, rs, probe0, n_probes, n_k, cref);
   else
     hipLaunchKernelGGL(ref_first_kernel<float2>, g, dim3(256), 0, st, (const float2*)in, pstride,
-                       probe0, n_probes, n_k, cref);
+                       nx, rs, probe0, n_probes, n_k, cref);
   return hipGetLastError();
 }
 
 // Exact FP64 time mean over frames [0, n_used) of each (probe, pixel).
 template <typename InT>
-__global__ void mean_kernel(const InT* in, int64_t pstride, int64_t fstride, int64_t n_used,
-                            int32_t probe0, int32_t n_probes, int32_t n_k, double2* out) {
+__global__ void mean_kernel(const InT* in, int64_t pstride, int64_t fstride, int32_t nx, int64_t rs,
+                            int64_t n_used, int32_t probe0, int32_t n_probes, int32_t n_k,
+                            double2* out) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (k >= n_k || i >= n_probes) return;
-  const InT* p = in + (int64_t)i * pstride + k;
+  const InT* p = in + (int64_t)i * pstride + pix_off(k, nx, rs);
   double sx = 0.0, sy = 0.0;
   for (int64_t n = 0; n < n_used; ++n) {
     const InT v = p[n * fstride];
@@ -70,31 +72,32 @@ __global__ void mean_kernel(const InT* in, int64_t pstride, int64_t fstride, int
 }
 
 hipError_t launch_mean_exact(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
-                             int64_t n_used, int32_t probe0, int32_t n_probes, int32_t n_k,
-                             double2* mu, hipStream_t st) {
+                             int32_t nx, int64_t rs, int64_t n_used, int32_t probe0,
+                             int32_t n_probes, int32_t n_k, double2* mu, hipStream_t st) {
   dim3 g((n_k + 255) / 256, n_probes);
   if (in_dtype == 1)
     hipLaunchKernelGGL(mean_kernel<double2>, g, dim3(256), 0, st, (const double2*)in, pstride,
-                       fstride, n_used, probe0, n_probes, n_k, mu);
+                       fstride, nx, rs, n_used, probe0, n_probes, n_k, mu);
   else
     hipLaunchKernelGGL(mean_kernel<float2>, g, dim3(256), 0, st, (const float2*)in, pstride,
-                       fstride, n_used, probe0, n_probes, n_k, mu);
+                       fstride, nx, rs, n_used, probe0, n_probes, n_k, mu);
   return hipGetLastError();
 }
 
 hipError_t launch_ref_mean(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
-                           int64_t n_used, int32_t probe0, int32_t n_probes, int32_t n_k,
-                           double2* cref, hipStream_t st) {
-  return launch_mean_exact(in, in_dtype, pstride, fstride, n_used, probe0, n_probes, n_k, cref,
-                           st);
+                           int32_t nx, int64_t rs, int64_t n_used, int32_t probe0,
+                           int32_t n_probes, int32_t n_k, double2* cref, hipStream_t st) {
+  return launch_mean_exact(in, in_dtype, pstride, fstride, nx, rs, n_used, probe0, n_probes, n_k,
+                           cref, st);
 }
 
 // ring[slot][f % D][k] = in[i][f - push_begin][k] for f in [f_lo, f_hi); each
 // thread copies 16 bytes (two complex64 or one complex128 element)
 template <typename InT>
-__global__ void ring_store_kernel(const InT* in, int64_t pstride, int64_t fstride,
-                                  int64_t push_begin, int64_t f_lo, int32_t n_f, int32_t probe0,
-                                  int32_t n_slots, int64_t depth, int32_t n_k, InT* ring) {
+__global__ void ring_store_kernel(const InT* in, int64_t pstride, int64_t fstride, int32_t nx,
+                                  int64_t rs, int64_t push_begin, int64_t f_lo, int32_t n_f,
+                                  int32_t probe0, int32_t n_slots, int64_t depth, int32_t n_k,
+                                  InT* ring) {
   constexpr int V = 16 / (int)sizeof(InT);  // elements per thread
   const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V;
   const int fi = blockIdx.y;
@@ -106,25 +109,25 @@ __global__ void ring_store_kernel(const InT* in, int64_t pstride, int64_t fstrid
   const InT* src = in + (int64_t)i * pstride + (f - push_begin) * fstride;
 #pragma unroll
   for (int v = 0; v < V; ++v)
-    if (k0 + v < n_k) dst[k0 + v] = src[k0 + v];
+    if (k0 + v < n_k) dst[k0 + v] = src[pix_off(k0 + v, nx, rs)];
 }
 
 hipError_t launch_ring_store(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
-                             int64_t push_begin, int64_t f_lo, int64_t f_hi, int32_t probe0,
-                             int32_t n_probes, int32_t n_slots, int64_t depth, int32_t n_k,
-                             void* ring, hipStream_t st) {
+                             int32_t nx, int64_t rs, int64_t push_begin, int64_t f_lo,
+                             int64_t f_hi, int32_t probe0, int32_t n_probes, int32_t n_slots,
+                             int64_t depth, int32_t n_k, void* ring, hipStream_t st) {
   const int64_t nf = f_hi - f_lo;
   if (nf <= 0) return hipSuccess;
   const int V = in_dtype == 1 ? 1 : 2;
   dim3 g((unsigned)((n_k + 256 * V - 1) / (256 * V)), (unsigned)nf, n_probes);
   if (in_dtype == 1)
     hipLaunchKernelGGL(ring_store_kernel<double2>, g, dim3(256), 0, st, (const double2*)in,
-                       pstride, fstride, push_begin, f_lo, (int32_t)nf, probe0, n_slots, depth,
-                       n_k, (double2*)ring);
+                       pstride, fstride, nx, rs, push_begin, f_lo, (int32_t)nf, probe0, n_slots,
+                       depth, n_k, (double2*)ring);
   else
     hipLaunchKernelGGL(ring_store_kernel<float2>, g, dim3(256), 0, st, (const float2*)in, pstride,
-                       fstride, push_begin, f_lo, (int32_t)nf, probe0, n_slots, depth, n_k,
-                       (float2*)ring);
+                       fstride, nx, rs, push_begin, f_lo, (int32_t)nf, probe0, n_slots, depth,
+                       n_k, (float2*)ring);
   return hipGetLastError();
 }
 

@@ -178,11 +178,14 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
   const int corr_b = (j == 0) ? 0 : (j == 1 ? 1 : 2);
   const bool corr_own = track && (j == 0 || (a.n_corr == 3 && (j == 1 || j == N2 - 1)));
   const int64_t row_bytes = a.fstride * ESZ;
+  // pixel kc inside an input frame (a k-space window may have wider pixel rows)
+  const int64_t kin = pix_off(kc, a.nx, a.row_stride);
   // per-lane byte offset inside a frame row group: (n2 rows down, kc pixels across)
-  const uint32_t lane_off = (uint32_t)(((int64_t)n2 * a.fstride + kc) * ESZ);
-  // bytes addressable from a row-group base: N2 - 1 full rows plus the pixels
-  // of the last row (the host checks that this fits in 32 bits)
-  const uint32_t group_bytes = (uint32_t)((int64_t)(N2 - 1) * row_bytes + (int64_t)n_k * ESZ);
+  const uint32_t lane_off = (uint32_t)(((int64_t)n2 * a.fstride + kin) * ESZ);
+  // bytes addressable from a row-group base: N2 - 1 full frames plus the span of
+  // the last frame's pixels (the host checks that this fits in 32 bits)
+  const int64_t span = pix_off((int64_t)n_k - 1, a.nx, a.row_stride) + 1;
+  const uint32_t group_bytes = (uint32_t)((int64_t)(N2 - 1) * row_bytes + span * ESZ);
 
   // LEAN: raw samples of the next chunk, loaded one chunk ahead (software prefetch)
   InT pre[LEAN ? N1 : 1];
@@ -261,7 +264,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
       auto fetch_any = [&](int n1) -> InT {
         const int64_t f = seg0 + N2 * n1 + n2;
         if (f >= a.push_begin)
-          return *(const InT*)(in_probe + (f - a.push_begin) * row_bytes + kc * ESZ);
+          return *(const InT*)(in_probe + (f - a.push_begin) * row_bytes + kin * ESZ);
         return ringb[(f % a.ring_depth) * (int64_t)n_k];
       };
       auto load_range = [&](int lo, auto fetch, auto cmode) {

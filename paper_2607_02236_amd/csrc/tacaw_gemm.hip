@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
     const float sc = gscale[(int64_t)p * n_k + ksc];
     const float sc_col = gscale[(int64_t)p * n_k + (cvalid ? kcol : (int64_t)n_k - 1)];
     const float inv2 = 1.0f / (sc_col * sc_col);
-    const InT* inb = (const InT*)a.in + (int64_t)i * a.pstride + ksc;
+    const InT* inb = (const InT*)a.in + (int64_t)i * a.pstride + pix_off(ksc, a.nx, a.row_stride);
 
     for (int s = a.s_lo; s < a.s_hi; ++s) {
       const int64_t seg0 = (int64_t)s * a.hop - a.push_begin;
@@ -287,13 +287,13 @@ hipError_t launch_seg_gemm(int L, int in_dtype, bool /*sub64*/, int prec, const 
 // over frames [0, n_used) (c = the subtracted reference), so |s (psi - c)| < 1/2
 // and fp16 low parts stay normal; s = 1 for bf16.
 template <typename InT>
-__global__ void gemm_scale_kernel(const InT* in, int64_t pstride, int64_t fstride, int64_t n_used,
-                                  int32_t probe0, int32_t n_probes, int32_t n_k, int32_t prec,
-                                  const double2* cref, float* scale) {
+__global__ void gemm_scale_kernel(const InT* in, int64_t pstride, int64_t fstride, int32_t nx,
+                                  int64_t rs, int64_t n_used, int32_t probe0, int32_t n_probes,
+                                  int32_t n_k, int32_t prec, const double2* cref, float* scale) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (k >= n_k || i >= n_probes) return;
-  const InT* p = in + (int64_t)i * pstride + k;
+  const InT* p = in + (int64_t)i * pstride + pix_off(k, nx, rs);
   const double2 c = cref[(int64_t)(probe0 + i) * n_k + k];
   double mx = 0.0;
   for (int64_t n = 0; n < n_used; ++n) {
@@ -311,15 +311,16 @@ __global__ void gemm_scale_kernel(const InT* in, int64_t pstride, int64_t fstrid
 }
 
 hipError_t launch_gemm_scale(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
-                             int64_t n_used, int32_t probe0, int32_t n_probes, int32_t n_k,
-                             int prec, const double2* cref, float* scale, hipStream_t st) {
+                             int32_t nx, int64_t rs, int64_t n_used, int32_t probe0,
+                             int32_t n_probes, int32_t n_k, int prec, const double2* cref,
+                             float* scale, hipStream_t st) {
   dim3 g((n_k + 255) / 256, n_probes);
   if (in_dtype == 1)
     hipLaunchKernelGGL(gemm_scale_kernel<double2>, g, dim3(256), 0, st, (const double2*)in, pstride,
-                       fstride, n_used, probe0, n_probes, n_k, prec, cref, scale);
+                       fstride, nx, rs, n_used, probe0, n_probes, n_k, prec, cref, scale);
   else
     hipLaunchKernelGGL(gemm_scale_kernel<float2>, g, dim3(256), 0, st, (const float2*)in, pstride,
-                       fstride, n_used, probe0, n_probes, n_k, prec, cref, scale);
+                       fstride, nx, rs, n_used, probe0, n_probes, n_k, prec, cref, scale);
   return hipGetLastError();
 }
 

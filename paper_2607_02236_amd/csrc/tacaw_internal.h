@@ -10,11 +10,20 @@ namespace tacaw {
 constexpr int kMaxDet = 8;   // detector masks per plan
 constexpr int kMaxCorr = 3;  // bins where the window's DFT is non-zero (Hann: 0, 1, L-1)
 
+// Element offset of pixel k inside one input frame whose ny rows of nx pixels are
+// rs elements apart (rs = nx: contiguous; rs > nx: a k-space window of a wider grid).
+__host__ __device__ __forceinline__ int64_t pix_off(int64_t k, int32_t nx, int64_t rs) {
+  return rs == nx ? k : (k / nx) * rs + k % nx;
+}
+
 // Arguments of the fused chunk kernels (FFT and GEMM forms).
 struct SegArgs {
-  const void* in;          // push buffer, element (i, n, k) at in + i*pstride + n*fstride + k
+  const void* in;          // push buffer, element (i, n, k) at in + i*pstride + n*fstride +
+                           // pix_off(k, nx, row_stride)
   int64_t pstride;         // elements
   int64_t fstride;         // elements
+  int64_t row_stride;      // elements between the input's pixel rows (ring: nx)
+  int32_t nx;
   int64_t push_begin;      // absolute frame index of the push buffer's frame 0
   const void* ring;        // [n_slots][D][n_k] frames pushed earlier, slot = probe % n_slots,
                            // frame f at row f mod D
@@ -59,20 +68,24 @@ hipError_t launch_seg_gemm(int L, int in_dtype, bool sub64, int prec, const SegA
 int seg_gemm_tile_pixels(int L);
 bool seg_gemm_supported(int L);
 hipError_t launch_gemm_scale(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
-                             int64_t n_used, int32_t probe0, int32_t n_probes, int32_t n_k,
-                             int prec, const double2* cref, float* scale, hipStream_t st);
+                             int32_t nx, int64_t rs, int64_t n_used, int32_t probe0,
+                             int32_t n_probes, int32_t n_k, int prec, const double2* cref,
+                             float* scale, hipStream_t st);
 
 // Auxiliary kernels (tacaw_aux.hip).
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
-hipError_t launch_ref_first_frame(const void* in, int in_dtype, int64_t pstride, int32_t probe0,
-                                  int32_t n_probes, int32_t n_k, double2* cref, hipStream_t st);
+// nx, rs: pixel rows of the input frames (see pix_off)
+hipError_t launch_ref_first_frame(const void* in, int in_dtype, int64_t pstride, int32_t nx,
+                                  int64_t rs, int32_t probe0, int32_t n_probes, int32_t n_k,
+                                  double2* cref, hipStream_t st);
 hipError_t launch_ref_mean(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
-                           int64_t n_used, int32_t probe0, int32_t n_probes, int32_t n_k,
-                           double2* cref, hipStream_t st);
+                           int32_t nx, int64_t rs, int64_t n_used, int32_t probe0,
+                           int32_t n_probes, int32_t n_k, double2* cref, hipStream_t st);
+// the ring holds contiguous frames (pixel k at row offset k)
 hipError_t launch_ring_store(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
-                             int64_t push_begin, int64_t f_lo, int64_t f_hi, int32_t probe0,
-                             int32_t n_probes, int32_t n_slots, int64_t depth, int32_t n_k,
-                             void* ring, hipStream_t st);
+                             int32_t nx, int64_t rs, int64_t push_begin, int64_t f_lo,
+                             int64_t f_hi, int32_t probe0, int32_t n_probes, int32_t n_slots,
+                             int64_t depth, int32_t n_k, void* ring, hipStream_t st);
 // det_off[d] .. det_off[d + 1]: the dpart slots of detector d (n_det + 1 entries)
 struct DetSlots {
   int32_t off[kMaxDet + 1];
@@ -105,6 +118,8 @@ hipError_t launch_detector(const double* S, const double* masks, int32_t n_det, 
 struct BwdArgs {
   const void* in;
   int64_t pstride, fstride;
+  int64_t row_stride;      // pixel rows of in and grad (see pix_off)
+  int32_t nx;
   void* grad;              // same layout as in
   int32_t n_k, probe0, n_probes, n_probe_total, n_seg, hop, n_det;
   int32_t n_om, roi_half;  // output rows and energy window (bin m -> row (m + M) mod L)
@@ -130,8 +145,8 @@ int bwd_tile_pixels(int L);
 hipError_t launch_bwd_mean_fix(const BwdArgs& a, int in_dtype, hipStream_t st);
 hipError_t launch_bwd_wparam(const double* part, int n, double c, double* out, hipStream_t st);
 hipError_t launch_mean_exact(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
-                             int64_t n_used, int32_t probe0, int32_t n_probes, int32_t n_k,
-                             double2* mu, hipStream_t st);
+                             int32_t nx, int64_t rs, int64_t n_used, int32_t probe0,
+                             int32_t n_probes, int32_t n_k, double2* mu, hipStream_t st);
 hipError_t launch_dot_gS(const double* S, const double* gS, int64_t n, double* out,
                          hipStream_t st);
 hipError_t launch_sum(const double* p, int64_t n, double* out, hipStream_t st);

@@ -197,6 +197,7 @@ struct tacaw_plan_s {
   hipEvent_t ev[kMaxTimed][2] = {};  // chunk-kernel timing, up to kMaxTimed launches per push
   int n_timed = 0;                    // launches timed in the last push
   int64_t D = 0;                      // ring depth (frames per slot)
+  int64_t rs = 0, span = 0;           // input pixel-row stride and elements spanned per frame
   bool deferred = false;              // deferred ring mode (ring_frames > seg_len)
   std::vector<int> s_done;            // deferred mode: chunks processed per probe
   bool s_fresh = true;                // no chunk launch since the last reset: S is undefined
@@ -265,6 +266,8 @@ static int run_chunks(tacaw_plan_t P, const void* src, int64_t pstride, int64_t 
   g.in = src;
   g.pstride = pstride;
   g.fstride = fstride;
+  g.nx = P->d.nx;
+  g.row_stride = from_ring ? P->d.nx : P->rs;  // the ring holds contiguous frames
   g.push_begin = from_ring ? ((int64_t)1 << 62) : push_begin;
   g.ring = P->ring;
   g.ring_depth = P->D;
@@ -363,6 +366,8 @@ int tacaw_plan_check(const tacaw_plan_desc* d) {
     return fail(TACAW_ERR_INVALID_ARG, "max_probes_in_flight must be in [0, n_probe]");
   if (d->omega_half < 0 || d->omega_half > d->seg_len / 2 - 1)
     return fail(TACAW_ERR_INVALID_ARG, "omega_half must be in [0, seg_len/2 - 1]");
+  if (d->k_row_stride != 0 && d->k_row_stride < d->nx)
+    return fail(TACAW_ERR_INVALID_ARG, "k_row_stride must be 0 or >= nx");
   if (d->ring_frames != 0) {
     if (d->ring_frames <= d->seg_len || d->ring_frames % (d->seg_len / 2) != 0)
       return fail(TACAW_ERR_INVALID_ARG,
@@ -401,6 +406,8 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   P->cursor.assign(d->n_probe, 0);
   P->s_done.assign(d->n_probe, 0);
   P->deferred = d->ring_frames > 0;
+  P->rs = d->k_row_stride > 0 ? d->k_row_stride : d->nx;
+  P->span = (int64_t)(d->ny - 1) * P->rs + d->nx;
   P->D = P->deferred ? d->ring_frames : P->L;
   P->n_slots = d->max_probes_in_flight > 0 ? d->max_probes_in_flight : d->n_probe;
   P->slot_owner.assign(P->n_slots, -1);
@@ -642,9 +649,10 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
   if (!frames) return fail(TACAW_ERR_INVALID_ARG, "frames is NULL");
   if (((uintptr_t)frames) % P->esz != 0)
     return fail(TACAW_ERR_INVALID_ARG, "frames pointer is not aligned to its element size");
-  if (fstride < P->n_k) return fail(TACAW_ERR_INVALID_ARG, "frame_stride must be >= ny * nx");
+  if (fstride < P->span)
+    return fail(TACAW_ERR_INVALID_ARG, "frame_stride must cover a frame ((ny - 1) * row stride + nx)");
   if (n_probes > 1 && pstride < 1) return fail(TACAW_ERR_INVALID_ARG, "probe_stride must be >= 1");
-  if (((int64_t)P->N2 * fstride + P->n_k) * P->esz > (int64_t)0x7FFFFFFFLL)
+  if (((int64_t)P->N2 * fstride + P->span) * P->esz > (int64_t)0x7FFFFFFFLL)
     return fail(TACAW_ERR_UNSUPPORTED, "frame_stride too large for 31-bit row-group offsets");
   const int64_t a = P->cursor[probe0];
   for (int i = 1; i < n_probes; ++i)
@@ -697,17 +705,18 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
   // 1. references at the first frame of each probe
   if (a == 0) {
     if (P->strategy == kRefFirstFrame)
-      TRY(hip_check(launch_ref_first_frame(frames, P->d.in_dtype, pstride, probe0, n_probes, P->n_k,
-                                           P->cref, P->st),
+      TRY(hip_check(launch_ref_first_frame(frames, P->d.in_dtype, pstride, P->d.nx, P->rs, probe0,
+                                           n_probes, P->n_k, P->cref, P->st),
                     "reference"));
     else if (P->strategy == kRefExactMean)
-      TRY(hip_check(launch_ref_mean(frames, P->d.in_dtype, pstride, fstride, P->n_used, probe0,
-                                    n_probes, P->n_k, P->cref, P->st),
+      TRY(hip_check(launch_ref_mean(frames, P->d.in_dtype, pstride, fstride, P->d.nx, P->rs,
+                                    P->n_used, probe0, n_probes, P->n_k, P->cref, P->st),
                     "mean pre-pass"));
     if (transform_is_gemm(P->d.transform))
-      TRY(hip_check(launch_gemm_scale(frames, P->d.in_dtype, pstride, fstride, P->n_used, probe0,
-                                      n_probes, P->n_k, P->d.transform == TACAW_GEMM_F16X3 ? 1 : 0,
-                                      P->cref, P->gscale, P->st),
+      TRY(hip_check(launch_gemm_scale(frames, P->d.in_dtype, pstride, fstride, P->d.nx, P->rs,
+                                      P->n_used, probe0, n_probes, P->n_k,
+                                      P->d.transform == TACAW_GEMM_F16X3 ? 1 : 0, P->cref,
+                                      P->gscale, P->st),
                     "operand scale pre-pass"));
   }
   P->n_timed = 0;
@@ -716,8 +725,9 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
     if (s_hi > s_lo) TRY(run_chunks(P, frames, pstride, fstride, a, false, probe0, n_probes, s_lo, s_hi));
     // 3. keep what later chunks need
     if (need_ring_write)
-      TRY(hip_check(launch_ring_store(frames, P->d.in_dtype, pstride, fstride, a, keep_lo, keep_hi,
-                                      probe0, n_probes, P->n_slots, P->D, P->n_k, P->ring, P->st),
+      TRY(hip_check(launch_ring_store(frames, P->d.in_dtype, pstride, fstride, P->d.nx, P->rs, a,
+                                      keep_lo, keep_hi, probe0, n_probes, P->n_slots, P->D,
+                                      P->n_k, P->ring, P->st),
                     "ring store"));
   } else {
     // deferred: completed chunks wait in the ring until this push would overwrite the
@@ -728,8 +738,8 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
       sd = s_lo;
     }
     if (need_ring_write)
-      TRY(hip_check(launch_ring_store(frames, P->d.in_dtype, pstride, fstride, a, a,
-                                      std::min<int64_t>(b, P->n_used), probe0, n_probes,
+      TRY(hip_check(launch_ring_store(frames, P->d.in_dtype, pstride, fstride, P->d.nx, P->rs, a,
+                                      a, std::min<int64_t>(b, P->n_used), probe0, n_probes,
                                       P->n_slots, P->D, P->n_k, P->ring, P->st),
                     "ring store"));
     if (b >= P->n_used && sd < P->Ns) {
@@ -834,7 +844,8 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
     return fail(TACAW_ERR_INVALID_ARG, "frames/grad not aligned to their element size");
   if (n_probes < 1 || probe0 < 0 || probe0 + (int64_t)n_probes > P->d.n_probe)
     return fail(TACAW_ERR_SHAPE, "probe range outside the plan");
-  if (fstride < P->n_k) return fail(TACAW_ERR_INVALID_ARG, "frame_stride must be >= ny * nx");
+  if (fstride < P->span)
+    return fail(TACAW_ERR_INVALID_ARG, "frame_stride must cover a frame ((ny - 1) * row stride + nx)");
   if (n_probes > 1 && pstride < 1) return fail(TACAW_ERR_INVALID_ARG, "probe_stride must be >= 1");
   if (P->H != P->L && 2 * P->H != P->L)
     return fail(TACAW_ERR_UNSUPPORTED, "backward supports hop = L or hop = L/2");
@@ -857,13 +868,15 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
     P->scratch_bytes = need;
   }
   if (global)
-    TRY(hip_check(launch_mean_exact(frames, P->d.in_dtype, pstride, fstride, P->n_used, probe0,
-                                    n_probes, P->n_k, P->mu, P->st),
+    TRY(hip_check(launch_mean_exact(frames, P->d.in_dtype, pstride, fstride, P->d.nx, P->rs,
+                                    P->n_used, probe0, n_probes, P->n_k, P->mu, P->st),
                   "adjoint mean"));
   BwdArgs b{};
   b.in = frames;
   b.pstride = pstride;
   b.fstride = fstride;
+  b.nx = P->d.nx;
+  b.row_stride = P->rs;
   b.grad = grad;
   b.n_k = P->n_k;
   b.probe0 = probe0;

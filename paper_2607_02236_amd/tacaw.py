@@ -42,7 +42,7 @@ class PlanDesc(C.Structure):
         ("n_det", C.c_int32), ("d_masks", C.c_void_p),
         ("max_probes_in_flight", C.c_int32), ("flags", C.c_int32),
         ("temperature_K", C.c_double), ("h_window", C.c_void_p),
-        ("ring_frames", C.c_int64), ("omega_half", C.c_int32),
+        ("ring_frames", C.c_int64), ("k_row_stride", C.c_int64), ("omega_half", C.c_int32),
     ]
 
 
@@ -96,11 +96,13 @@ def _check(rc):
 def make_desc(n_probe, ny, nx, n_frames, seg_len, hop, window="hann", window_param=1.0,
               mean_mode="global", transform="fft", in_dtype="c64", probe_reduce="mean",
               dt_fs=5.0, n_det=0, masks_ptr=0, max_probes_in_flight=0, flags=0,
-              temperature_K=0.0, window_values=None, omega_half=0, ring_frames=0) -> PlanDesc:
+              temperature_K=0.0, window_values=None, omega_half=0, ring_frames=0,
+              k_row_stride=0) -> PlanDesc:
     """window may be a name or an array of seg_len values (custom window).
     omega_half = M > 0 keeps only the 2M + 1 bins of signed index -M..M
     (ascending); axes.omega_half_for converts a frequency or energy limit.
-    ring_frames > seg_len selects the deferred streaming mode (see include/tacaw.h)."""
+    ring_frames > seg_len selects the deferred streaming mode (see include/tacaw.h);
+    k_row_stride > nx reads a ny x nx k-space window of a wider grid in place."""
     wptr = None
     if not isinstance(window, str):
         import numpy as np
@@ -114,7 +116,7 @@ def make_desc(n_probe, ny, nx, n_frames, seg_len, hop, window="hann", window_par
                  TRANSFORMS[transform], DTYPES[in_dtype], REDUCE[probe_reduce],
                  float(dt_fs), int(n_det), C.c_void_p(masks_ptr or None),
                  int(max_probes_in_flight), int(flags), float(temperature_K), C.c_void_p(wptr),
-                 int(ring_frames), int(omega_half))
+                 int(ring_frames), int(k_row_stride), int(omega_half))
     d._window_values = window_values  # keep the host array alive with the descriptor
     return d
 
@@ -142,7 +144,7 @@ class Plan:
                  window_param=1.0, mean_mode="global", transform="fft", in_dtype="c64",
                  probe_reduce="mean", dt_fs=5.0, masks=None, max_probes_in_flight=0,
                  stream=None, time_kernels=False, temperature_K=0.0, omega_half=0,
-                 ring_frames=0):
+                 ring_frames=0, k_row_stride=0):
         self.handle = None
         hop = seg_len // 2 if hop is None else hop
         self.n_probe, self.ny, self.nx = int(n_probe), int(ny), int(nx)
@@ -164,7 +166,9 @@ class Plan:
         self.desc = make_desc(n_probe, ny, nx, n_frames, seg_len, hop, window, window_param,
                               mean_mode, transform, in_dtype, probe_reduce, dt_fs, n_det, mptr,
                               max_probes_in_flight, 1 if time_kernels else 0, temperature_K,
-                              omega_half=omega_half, ring_frames=ring_frames)
+                              omega_half=omega_half, ring_frames=ring_frames,
+                              k_row_stride=k_row_stride)
+        self.row_stride = int(k_row_stride) or self.nx
         h = C.c_void_p()
         _check(lib.tacaw_plan(C.byref(self.desc), sptr, C.byref(h)))
         self.handle = h
@@ -191,8 +195,8 @@ class Plan:
             frames = frames[None]
         if frames.dim() != 4 or tuple(frames.shape[2:]) != (self.ny, self.nx):
             raise ValueError("frames must be [n_probes, n_frames, ny, nx]")
-        if frames.stride(3) != 1 or frames.stride(2) != self.nx:
-            raise ValueError("each frame must be a contiguous ny x nx image")
+        if frames.stride(3) != 1 or frames.stride(2) != self.row_stride:
+            raise ValueError("pixel rows must be contiguous and k_row_stride apart")
         return frames, frames.stride(0), frames.stride(1)
 
     def push(self, frames: torch.Tensor, probe0: int = 0):
@@ -238,7 +242,8 @@ class Plan:
         if frames.shape[1] < self.info()["frames_used"]:
             raise ValueError("backward needs every frame that enters a chunk (frames_used)")
         if grad is None:
-            grad = torch.zeros_like(frames)
+            grad = torch.empty_strided(frames.shape, frames.stride(), dtype=frames.dtype,
+                                       device=frames.device).zero_()
         if grad.stride() != frames.stride():
             raise ValueError("grad must have the strides of frames")
         if grad_wparam is None:

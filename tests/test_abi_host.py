@@ -59,6 +59,7 @@ def _ok(**over):
     (dict(temperature_K=-1.0), "INVALID_ARG"),
     (dict(transform="gemm_f16x3", seg_len=1024, n_frames=2048, hop=512), "UNSUPPORTED"),
     (dict(omega_half=-1), "INVALID_ARG"),
+    (dict(k_row_stride=7), "INVALID_ARG"),    # k window: row stride below nx
     (dict(ring_frames=128), "INVALID_ARG"),   # must exceed seg_len
     (dict(ring_frames=160), "INVALID_ARG"),   # multiple of seg_len / 2
     (dict(ring_frames=256, transform="gemm_f16x3"), "UNSUPPORTED"),
@@ -85,6 +86,7 @@ def test_valid_descriptors_pass():
     tacaw.check_desc(**_ok(transform="gemm_bf16x3"))
     tacaw.check_desc(**_ok(omega_half=63))
     tacaw.check_desc(**_ok(ring_frames=192))
+    tacaw.check_desc(**_ok(k_row_stride=40))
     tacaw.check_desc(**_ok(seg_len=200, hop=100, n_frames=3200, dt_fs=15.0, omega_half=90))
     tacaw.check_desc(**_ok(omega_half=1, transform="gemm_f16x3", temperature_K=50.0))
 

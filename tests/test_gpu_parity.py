@@ -369,3 +369,46 @@ def test_deferred_ring_mode_errors(tacaw):
     with pytest.raises(tacaw.TacawError) as e:  # non-compact window: exact-mean pre-pass
         tacaw.Plan(1, 4, 4, 640, 128, 64, window="tukey", window_param=0.5, ring_frames=256)
     assert e.value.kind == "UNSUPPORTED"
+
+
+@pytest.mark.parametrize("ring", [0, 256])
+def test_k_space_window_read_in_place(tacaw, ring):
+    # Sec. II.B crops reciprocal space to a region of interest: a ny x nx window of a
+    # wider grid is read in place (pixel rows k_row_stride apart), equal to the
+    # reduction of the cropped copy
+    big = T.generate(T.SeriesSpec(2, 640, 20, 33, dtype="c64", seed=61, model="lines", n_terms=8))
+    y0, x0, ny, nx = 3, 5, 11, 17
+    masks = T.standard_masks(ny, nx, scale=0.05)
+    crop = big[:, :, y0:y0 + ny, x0:x0 + nx].contiguous()
+    ref = run_gpu(tacaw, crop, 128, 64, masks)
+    dev = big.cuda()
+    view = dev[:, :, y0:y0 + ny, x0:x0 + nx]
+    plan = tacaw.Plan(2, ny, nx, 640, 128, 64, masks=torch.from_numpy(masks).cuda(),
+                      k_row_stride=33, ring_frames=ring)
+    for f0 in range(0, 640, 64):
+        plan.push(view[:, f0:f0 + 64])
+    S = plan.finalize().cpu().numpy().reshape(128, -1)
+    D, Dp = plan.detector_spectra(per_probe=True)
+    plan.close()
+    assert rel(S, ref["S"]) < 1e-12 and rel(Dp.cpu().numpy(), ref["Dp"]) < 1e-12
+    check({"S": S, "D": D.cpu().numpy(), "Dp": Dp.cpu().numpy()},
+          oracle_all(crop, 128, 64, masks=masks), label=f"k window ring={ring}")
+
+
+def test_k_space_window_adjoint(tacaw):
+    from paper_2607_02236_amd import tacaw as tw
+
+    big = T.generate(T.SeriesSpec(1, 256, 12, 20, dtype="c64", seed=62, model="lines", n_terms=8))
+    y0, x0, ny, nx = 2, 3, 8, 9
+    dev = big.cuda()
+    view = dev[:, :, y0:y0 + ny, x0:x0 + nx]
+    gS = torch.rand((128, ny, nx), dtype=torch.float64, device="cuda")
+    outs = []
+    for frames, rs in ((view, 20), (view.contiguous(), 0)):
+        plan = tw.Plan(1, ny, nx, 256, 128, 128, k_row_stride=rs)
+        plan.push(frames)
+        plan.finalize()
+        g, _ = plan.backward(frames, gS=gS)
+        outs.append(g[:, :, :, :].contiguous().cpu().numpy())
+        plan.close()
+    assert np.array_equal(outs[0], outs[1])
