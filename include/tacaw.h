@@ -171,6 +171,29 @@ int tacaw_plan_check(const tacaw_plan_desc* desc);
 int tacaw_push_frames(tacaw_plan_t plan, const void* d_frames, int32_t probe0, int32_t n_probes,
                       int64_t n_frames, int64_t probe_stride, int64_t frame_stride);
 
+/* Zero-copy ingest (deferred ring mode only): a producer writes the next n_frames
+ * frames of probes [probe0, probe0 + n_probes) straight into the plan's ring
+ * instead of pushing a buffer (so frames never exist twice in HBM). On return
+ * *d_dst points at frame cursor of probe probe0; element (i, n, k) goes to
+ * *d_dst + i * (*probe_stride) + n * (*frame_stride) + k (elements of in_dtype,
+ * contiguous ny * nx frames). Chunk launches that must read the overwritten
+ * rows first are enqueued before returning, so the producer writes on the
+ * plan's stream (or after synchronizing with it), then calls
+ * tacaw_commit_frames with the same arguments; no other push, ingest or finalize
+ * may come in between. Conditions: 1 <= n_frames <= ring_frames - seg_len; the
+ * rows do not wrap (cursor mod ring_frames + n_frames <= ring_frames); probe0 mod
+ * max_probes_in_flight + n_probes <= max_probes_in_flight; frames end at or
+ * before frames_used.
+ * Errors: INVALID_ARG, STATE (not deferred, ingest open, cursors differ, ring
+ * slots taken), SHAPE (sizes above), OOM, HIP. */
+int tacaw_ingest_frames(tacaw_plan_t plan, int32_t probe0, int32_t n_probes, int64_t n_frames,
+                        void** d_dst, int64_t* probe_stride, int64_t* frame_stride);
+
+/* Mark the frames handed out by the open tacaw_ingest_frames as written: the
+ * reference of a probe's first frame is taken and, at the end of a series, its
+ * remaining chunks run. Errors: STATE (no matching ingest), HIP. */
+int tacaw_commit_frames(tacaw_plan_t plan, int32_t probe0, int32_t n_probes, int64_t n_frames);
+
 /* Finish the reduction once every probe's series has been pushed: applies the
  * exact elastic-mean correction, normalises per voxel by 1 / (L sum_t w^2) and
  * averages over chunks (and probes, Eq. 2). Writes S(m, k) as float64

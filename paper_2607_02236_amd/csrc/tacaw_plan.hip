@@ -201,6 +201,9 @@ struct tacaw_plan_s {
   bool deferred = false;              // deferred ring mode (ring_frames > seg_len)
   std::vector<int> s_done;            // deferred mode: chunks processed per probe
   bool s_fresh = true;                // no chunk launch since the last reset: S is undefined
+  bool ingest_open = false;           // tacaw_ingest_frames handed out ring rows
+  int ingest_p0 = 0, ingest_np = 0;
+  int64_t ingest_nf = 0;
 
   int alloc(void** p, int64_t bytes, const char* what) {
     if (bytes <= 0) {
@@ -315,6 +318,72 @@ static int run_chunks(tacaw_plan_t P, const void* src, int64_t pstride, int64_t 
     TRY(hip_check(launch_dpart_reduce(P->dpart, P->det_slots, n_probes, P->d.n_det, P->n_om,
                                       probe0, P->d.n_probe, P->Dp, P->st),
                   "detector partial reduce"));
+  return TACAW_OK;
+}
+
+// Deferred mode, before frames [a, b) of a probe group enter the ring: completed
+// chunks wait there until these rows would overwrite the oldest of them; then all
+// completed chunks run in one launch.
+static int deferred_make_room(tacaw_plan_t P, int probe0, int n_probes, int64_t a, int64_t b) {
+  const int s_ready = (int)std::min<int64_t>(P->Ns, seg_count(a, P->L, P->H));
+  const int sd = P->s_done[probe0];
+  if (sd < s_ready && (int64_t)sd * P->H < b - P->D) {
+    TRY(run_chunks(P, P->ring, 0, P->n_k, 0, true, probe0, n_probes, sd, s_ready));
+    for (int i = 0; i < n_probes; ++i) P->s_done[probe0 + i] = s_ready;
+  }
+  return TACAW_OK;
+}
+
+// Deferred mode, after frames up to b are in the ring: at the end of the series
+// the remaining chunks run.
+static int deferred_finish(tacaw_plan_t P, int probe0, int n_probes, int64_t b) {
+  const int sd = P->s_done[probe0];
+  if (b >= P->n_used && sd < P->Ns) {
+    TRY(run_chunks(P, P->ring, 0, P->n_k, 0, true, probe0, n_probes, sd, P->Ns));
+    for (int i = 0; i < n_probes; ++i) P->s_done[probe0 + i] = P->Ns;
+  }
+  return TACAW_OK;
+}
+
+// Cursor and ring-slot bookkeeping after frames [a, b) of a probe group.
+static void advance(tacaw_plan_t P, int probe0, int n_probes, int64_t a, int64_t b, bool ring_used) {
+  for (int i = 0; i < n_probes; ++i) {
+    const int p = probe0 + i, sl = p % P->n_slots;
+    P->cursor[p] = b;
+    if (b >= P->n_used) {
+      if (P->slot_owner[sl] == p) P->slot_owner[sl] = -1;
+    } else if (ring_used) {
+      P->slot_owner[sl] = p;
+    }
+  }
+  P->dropped += (int64_t)n_probes * std::max<int64_t>(0, b - std::max<int64_t>(a, P->n_used));
+}
+
+// Ring slots of a probe group are free or already theirs.
+static int claim_slots(tacaw_plan_t P, int probe0, int n_probes) {
+  if (n_probes > P->n_slots)
+    return fail(TACAW_ERR_STATE, "ring capacity exceeded: more probes in flight than ring slots");
+  for (int i = 0; i < n_probes; ++i) {
+    const int p = probe0 + i, sl = p % P->n_slots;
+    if (P->slot_owner[sl] != -1 && P->slot_owner[sl] != p)
+      return fail(TACAW_ERR_STATE, "ring capacity exceeded: too many probes in flight");
+  }
+  if (!P->ring) {
+    const int64_t rb = (int64_t)P->n_slots * P->D * P->n_k * P->esz;
+    TRY(P->alloc(&P->ring, rb, "frame ring"));
+  }
+  return TACAW_OK;
+}
+
+static int ensure_dpart(tacaw_plan_t P, int n_probes) {
+  if (P->d.n_det == 0) return TACAW_OK;
+  const int64_t need = (int64_t)std::max(P->n_pairs, 1) * n_probes * P->n_om * 8;
+  if (need > P->dpart_bytes) {
+    P->release((void**)&P->dpart);
+    P->dpart_bytes = 0;
+    TRY(P->alloc((void**)&P->dpart, need, "detector partials"));
+    P->dpart_bytes = need;
+  }
   return TACAW_OK;
 }
 
@@ -591,6 +660,7 @@ int tacaw_reset(tacaw_plan_t P) {
   std::fill(P->cursor.begin(), P->cursor.end(), 0);
   std::fill(P->s_done.begin(), P->s_done.end(), 0);
   P->s_fresh = true;
+  P->ingest_open = false;
   std::fill(P->slot_owner.begin(), P->slot_owner.end(), -1);
   P->state = 0;
   P->dropped = 0;
@@ -642,6 +712,7 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
   g_err.clear();
   if (!P) return fail(TACAW_ERR_INVALID_ARG, "plan is NULL");
   if (P->state != 0) return fail(TACAW_ERR_STATE, "plan is finalized");
+  if (P->ingest_open) return fail(TACAW_ERR_STATE, "an ingest is open: commit it first");
   if (n_frames < 0) return fail(TACAW_ERR_INVALID_ARG, "n_frames must be >= 0");
   if (n_probes < 1 || probe0 < 0 || probe0 + (int64_t)n_probes > P->d.n_probe)
     return fail(TACAW_ERR_SHAPE, "probe range outside the plan");
@@ -679,28 +750,8 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
   const int64_t keep_hi = std::min<int64_t>(b, P->n_used);
   const bool need_ring_write = P->deferred ? a < P->n_used : (s_hi < P->Ns && keep_hi > keep_lo);
   const bool need_ring_read = P->deferred || (s_hi > s_lo && (int64_t)s_lo * P->H < a);
-  if (need_ring_write || need_ring_read) {
-    if (n_probes > P->n_slots)
-      return fail(TACAW_ERR_STATE, "ring capacity exceeded: more probes in flight than ring slots");
-    for (int i = 0; i < n_probes; ++i) {
-      const int p = probe0 + i, sl = p % P->n_slots;
-      if (P->slot_owner[sl] != -1 && P->slot_owner[sl] != p)
-        return fail(TACAW_ERR_STATE, "ring capacity exceeded: too many probes in flight");
-    }
-    if (!P->ring) {
-      const int64_t rb = (int64_t)P->n_slots * P->D * P->n_k * P->esz;
-      TRY(P->alloc(&P->ring, rb, "frame ring"));
-    }
-  }
-  if (P->d.n_det > 0) {
-    const int64_t dpart_need = (int64_t)std::max(P->n_pairs, 1) * n_probes * P->n_om * 8;
-    if (dpart_need > P->dpart_bytes) {
-      P->release((void**)&P->dpart);
-      P->dpart_bytes = 0;
-      TRY(P->alloc((void**)&P->dpart, dpart_need, "detector partials"));
-      P->dpart_bytes = dpart_need;
-    }
-  }
+  if (need_ring_write || need_ring_read) TRY(claim_slots(P, probe0, n_probes));
+  TRY(ensure_dpart(P, n_probes));
 
   // 1. references at the first frame of each probe
   if (a == 0) {
@@ -730,34 +781,73 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
                                       P->n_k, P->ring, P->st),
                     "ring store"));
   } else {
-    // deferred: completed chunks wait in the ring until this push would overwrite the
-    // oldest of them (then all completed ones run in one launch) or the series ends
-    int sd = P->s_done[probe0];
-    if (sd < s_lo && (int64_t)sd * P->H < b - P->D) {
-      TRY(run_chunks(P, P->ring, 0, P->n_k, 0, true, probe0, n_probes, sd, s_lo));
-      sd = s_lo;
-    }
+    // deferred: the push is copied into the ring; completed chunks run from there
+    TRY(deferred_make_room(P, probe0, n_probes, a, b));
     if (need_ring_write)
       TRY(hip_check(launch_ring_store(frames, P->d.in_dtype, pstride, fstride, P->d.nx, P->rs, a,
                                       a, std::min<int64_t>(b, P->n_used), probe0, n_probes,
                                       P->n_slots, P->D, P->n_k, P->ring, P->st),
                     "ring store"));
-    if (b >= P->n_used && sd < P->Ns) {
-      TRY(run_chunks(P, P->ring, 0, P->n_k, 0, true, probe0, n_probes, sd, P->Ns));
-      sd = P->Ns;
-    }
-    for (int i = 0; i < n_probes; ++i) P->s_done[probe0 + i] = sd;
+    TRY(deferred_finish(P, probe0, n_probes, b));
   }
-  for (int i = 0; i < n_probes; ++i) {
-    const int p = probe0 + i, sl = p % P->n_slots;
-    P->cursor[p] = b;
-    if (b >= P->n_used) {
-      if (P->slot_owner[sl] == p) P->slot_owner[sl] = -1;
-    } else if (need_ring_write || need_ring_read) {
-      P->slot_owner[sl] = p;
-    }
+  advance(P, probe0, n_probes, a, b, need_ring_write || need_ring_read);
+  return TACAW_OK;
+}
+
+int tacaw_ingest_frames(tacaw_plan_t P, int32_t probe0, int32_t n_probes, int64_t n_frames,
+                        void** d_dst, int64_t* probe_stride, int64_t* frame_stride) {
+  g_err.clear();
+  if (!P || !d_dst || !probe_stride || !frame_stride)
+    return fail(TACAW_ERR_INVALID_ARG, "plan and output pointers must not be NULL");
+  *d_dst = nullptr;
+  if (P->state != 0) return fail(TACAW_ERR_STATE, "plan is finalized");
+  if (!P->deferred) return fail(TACAW_ERR_STATE, "ingest needs the deferred ring mode");
+  if (P->ingest_open) return fail(TACAW_ERR_STATE, "the previous ingest is not committed");
+  if (n_probes < 1 || probe0 < 0 || probe0 + (int64_t)n_probes > P->d.n_probe)
+    return fail(TACAW_ERR_SHAPE, "probe range outside the plan");
+  if (n_frames < 1 || n_frames > P->D - P->L)
+    return fail(TACAW_ERR_SHAPE, "an ingest holds 1 .. ring_frames - seg_len frames");
+  const int64_t a = P->cursor[probe0], b = a + n_frames;
+  for (int i = 1; i < n_probes; ++i)
+    if (P->cursor[probe0 + i] != a || P->s_done[probe0 + i] != P->s_done[probe0])
+      return fail(TACAW_ERR_STATE, "probes of one ingest must be at the same frame cursor");
+  if (b > P->n_used) return fail(TACAW_ERR_SHAPE, "ingest goes beyond the frames the chunks use");
+  if (a % P->D + n_frames > P->D)
+    return fail(TACAW_ERR_SHAPE, "ingest would wrap around the ring (align pieces to ring_frames)");
+  if (probe0 % P->n_slots + n_probes > P->n_slots)
+    return fail(TACAW_ERR_SHAPE, "ingest probes must occupy consecutive ring slots");
+  TRY(claim_slots(P, probe0, n_probes));
+  TRY(ensure_dpart(P, n_probes));
+  TRY(deferred_make_room(P, probe0, n_probes, a, b));
+  const int64_t slot0 = probe0 % P->n_slots;
+  *d_dst = (char*)P->ring + ((slot0 * P->D + a % P->D) * P->n_k) * P->esz;
+  *probe_stride = P->D * P->n_k;
+  *frame_stride = P->n_k;
+  P->ingest_open = true;
+  P->ingest_p0 = probe0;
+  P->ingest_np = n_probes;
+  P->ingest_nf = n_frames;
+  return TACAW_OK;
+}
+
+int tacaw_commit_frames(tacaw_plan_t P, int32_t probe0, int32_t n_probes, int64_t n_frames) {
+  g_err.clear();
+  if (!P) return fail(TACAW_ERR_INVALID_ARG, "plan is NULL");
+  if (!P->ingest_open || P->ingest_p0 != probe0 || P->ingest_np != n_probes ||
+      P->ingest_nf != n_frames)
+    return fail(TACAW_ERR_STATE, "commit does not match the open ingest");
+  P->ingest_open = false;
+  const int64_t a = P->cursor[probe0], b = a + n_frames;
+  P->n_timed = 0;
+  if (a == 0 && P->strategy == kRefFirstFrame) {  // reference: frame 0, now in the ring
+    const int64_t slot0 = probe0 % P->n_slots;
+    TRY(hip_check(launch_ref_first_frame((char*)P->ring + slot0 * P->D * P->n_k * P->esz,
+                                         P->d.in_dtype, P->D * P->n_k, P->d.nx, P->d.nx, probe0,
+                                         n_probes, P->n_k, P->cref, P->st),
+                  "reference"));
   }
-  P->dropped += (int64_t)n_probes * std::max<int64_t>(0, b - std::max<int64_t>(a, P->n_used));
+  TRY(deferred_finish(P, probe0, n_probes, b));
+  advance(P, probe0, n_probes, a, b, true);
   return TACAW_OK;
 }
 
@@ -789,6 +879,7 @@ int tacaw_finalize(tacaw_plan_t P, double* d_S) {
   g_err.clear();
   if (!P) return fail(TACAW_ERR_INVALID_ARG, "plan is NULL");
   if (P->state != 0) return fail(TACAW_ERR_STATE, "plan is already finalized");
+  if (P->ingest_open) return fail(TACAW_ERR_STATE, "an ingest is open: commit it first");
   for (int p = 0; p < P->d.n_probe; ++p)
     if (P->cursor[p] < P->n_used)
       return fail(TACAW_ERR_STATE, "series incomplete for probe " + std::to_string(p));

@@ -68,6 +68,9 @@ def _load():
         "tacaw_finalize": (C.c_int, [P, P]),
         "tacaw_detector_spectra": (C.c_int, [P, P, C.c_int32, P, P]),
         "tacaw_backward": (C.c_int, [P, P, C.c_int32, C.c_int32, C.c_int64, C.c_int64, P, P, P, P, P]),
+        "tacaw_ingest_frames": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int64, C.POINTER(P),
+                                          C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+        "tacaw_commit_frames": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int64]),
         "tacaw_reset": (C.c_int, [P]),
         "tacaw_set_stream": (C.c_int, [P, P]),
         "tacaw_plan_get_info": (C.c_int, [P, C.POINTER(PlanInfo)]),
@@ -83,7 +86,8 @@ def _load():
 
 
 lib = _load()
-EXPORTED = ("tacaw_plan", "tacaw_plan_check", "tacaw_push_frames", "tacaw_finalize",
+EXPORTED = ("tacaw_plan", "tacaw_plan_check", "tacaw_push_frames", "tacaw_ingest_frames",
+            "tacaw_commit_frames", "tacaw_finalize",
             "tacaw_detector_spectra", "tacaw_backward", "tacaw_reset", "tacaw_set_stream",
             "tacaw_plan_get_info", "tacaw_destroy", "tacaw_last_error", "tacaw_version")
 
@@ -125,6 +129,14 @@ def check_desc(**kw) -> None:
     """Host-only validation of a plan descriptor (raises TacawError)."""
     d = make_desc(**kw)
     _check(lib.tacaw_plan_check(C.byref(d)))
+
+
+class _DeviceView:
+    """Device memory owned by the plan, exposed through the CUDA array interface."""
+
+    def __init__(self, ptr, shape, strides, typestr):
+        self.__cuda_array_interface__ = {"shape": shape, "strides": strides, "typestr": typestr,
+                                         "data": (ptr, False), "version": 3}
 
 
 def _stream_ptr(stream):
@@ -208,6 +220,25 @@ class Plan:
                                      int(frames.shape[0]), int(frames.shape[1]), int(ps), int(fs)))
         if self.stream != torch.cuda.current_stream():
             frames.record_stream(self.stream)
+
+    def ingest(self, n_frames: int, probe0: int = 0, n_probes: int = 1) -> torch.Tensor:
+        """Zero-copy ingest: a [n_probes, n_frames, ny, nx] CUDA tensor that aliases the
+        plan's ring; write the next frames into it on the plan's stream, then commit()."""
+        ptr, ps, fs = C.c_void_p(), C.c_int64(), C.c_int64()
+        _check(lib.tacaw_ingest_frames(self.handle, int(probe0), int(n_probes), int(n_frames),
+                                       C.byref(ptr), C.byref(ps), C.byref(fs)))
+        esz = 8 if self.in_dtype == "c64" else 16
+        view = _DeviceView(ptr.value, (int(n_probes), int(n_frames), self.ny, self.nx),
+                           (ps.value * esz, fs.value * esz, self.nx * esz, esz),
+                           "<c8" if self.in_dtype == "c64" else "<c16")
+        self._ingest = (int(probe0), int(n_probes), int(n_frames))
+        return torch.as_tensor(view, device="cuda")
+
+    def commit(self):
+        """Mark the frames of the last ingest() as written."""
+        p0, n, nf = self._ingest
+        _check(lib.tacaw_commit_frames(self.handle, p0, n, nf))
+        self._ingest = None
 
     def finalize(self, out: torch.Tensor | None = None) -> torch.Tensor:
         if out is None:

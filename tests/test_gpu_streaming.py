@@ -57,3 +57,61 @@ def test_streaming_pushes_match_oracle(n_probe, batch, grid, chunk, ring):
           f"mean(Dp) {eDp:.2e}")
     assert e <= 1e-5 and eD <= 1e-12 and eDp <= 1e-12
     plan.close()
+
+
+def test_zero_copy_ingest_generator_writes_into_ring():
+    # the seeded generator (the producer) writes each piece straight into the
+    # plan's ring; results equal pushing the same series, and the oracle
+    from paper_2607_02236_amd import tacaw
+
+    spec = T.SeriesSpec(3, 640, 10, 12, dtype="c64", seed=71, model="lines", n_terms=8)
+    L, H, D, piece = 128, 64, 256, 64
+    masks = torch.from_numpy(T.standard_masks(10, 12, scale=0.06)).cuda()
+    psi = T.generate(spec)
+    ref = tacaw.Plan(3, 10, 12, 640, L, H, masks=masks)
+    ref.push(psi.cuda())
+    S_ref = ref.finalize()
+    _, Dp_ref = ref.detector_spectra(per_probe=True)
+    plan = tacaw.Plan(3, 10, 12, 640, L, H, masks=masks, ring_frames=D, max_probes_in_flight=2)
+    for p0, n in ((0, 2), (2, 1)):
+        for f0 in range(0, 640, piece):
+            view = plan.ingest(piece, probe0=p0, n_probes=n)
+            for i in range(n):
+                view[i] = T.generate(spec, [p0 + i], (f0, f0 + piece), device="cuda")[0]
+            plan.commit()
+    S = plan.finalize()
+    _, Dp = plan.detector_spectra(per_probe=True)
+    torch.cuda.synchronize()
+    assert rel(S.cpu(), S_ref.cpu()) < 1e-12 and rel(Dp.cpu(), Dp_ref.cpu()) < 1e-12
+    So, _ = O.tacaw_spectra(psi.numpy(), L, H, O.window("hann", L))
+    e = rel(S.cpu().numpy().reshape(L, -1), So)
+    print(f"zero-copy ingest: S {e:.2e}")
+    assert e <= 1e-5
+    ref.close()
+    plan.close()
+
+
+def test_zero_copy_ingest_errors():
+    from paper_2607_02236_amd import tacaw
+
+    imm = tacaw.Plan(1, 4, 4, 512, 128, 64)
+    with pytest.raises(tacaw.TacawError) as e:
+        imm.ingest(64)
+    assert e.value.kind == "STATE"
+    imm.close()
+    plan = tacaw.Plan(2, 4, 4, 512, 128, 64, ring_frames=256)
+    with pytest.raises(tacaw.TacawError) as e:
+        plan.ingest(129)  # more than ring_frames - seg_len
+    assert e.value.kind == "SHAPE"
+    v = plan.ingest(96, n_probes=2)
+    v.fill_(1.0)
+    with pytest.raises(tacaw.TacawError) as e:
+        plan.push(torch.ones((2, 8, 4, 4), dtype=torch.complex64, device="cuda"))
+    assert e.value.kind == "STATE"  # an ingest is open
+    plan.commit()
+    with pytest.raises(tacaw.TacawError) as e:
+        plan.ingest(128, n_probes=2)  # rows 96..223 fit; 96 + 128 = 224 <= 256 is fine
+        plan.commit()
+        plan.ingest(64, n_probes=2)   # rows 224..287 would wrap
+    assert e.value.kind == "SHAPE"
+    plan.close()
