@@ -65,23 +65,25 @@ __device__ __forceinline__ f32x16 mfma(h8 a, h8 b, f32x16 c) {
 // output row r (bin (r - roi_half) mod L), zero rows up to m_rows (a multiple of 32);
 // column 2t + c' (c' = 0 multiplies Re y, 1 multiplies Im y).
 // gscale: [n_probe][n_k] float, the power-of-two scale s of y.
-template <int L, typename InT, int PREC, bool DP>
+// MBW: row blocks per wave (at most); NB: 32-pixel column blocks per workgroup. Fewer
+// rows (an energy window) leave room for more columns, so each DFT-matrix fragment
+// read from L2 feeds NB products.
+template <int L, typename InT, int PREC, bool DP, int MBW, int NB>
 __global__ void __launch_bounds__(64 * kGemmWaves)
     seg_gemm_kernel(const SegArgs a, const unsigned short* __restrict__ fmat, int m_rows,
                     const float* __restrict__ gscale) {
   constexpr int NT = 64 * kGemmWaves;
-  constexpr int MB = L / 16;            // row blocks of 32 rows at most (2L rows)
-  constexpr int MBW = MB / kGemmWaves;  // row blocks per wave at most
-  constexpr int KC = L < kGemmKC ? L : kGemmKC;
-  constexpr int KSTEPS = KC / 8;        // 16 real K (8 frames) per MFMA
+  constexpr int PX = kGemmPx * NB;              // pixels per workgroup
+  constexpr int KC = L < kGemmKC / NB ? L : kGemmKC / NB;  // frames per LDS stage
+  constexpr int KSTEPS = KC / 8;                // 16 real K (8 frames) per MFMA
   constexpr int K2 = 2 * L;
-  static_assert(MBW >= 1 && MB % kGemmWaves == 0, "row blocks per wave");
+  constexpr int SG = NT / PX;                   // staging groups of 4 frames
+  static_assert(MBW >= 1 && MBW * kGemmWaves * 32 <= 2 * L, "row blocks per wave");
+  static_assert(L % KC == 0 && SG >= 1, "staging");
 
-  // B operand staging: [kstep][lane][8] hi, then the same for lo, 16-bit
-  __shared__ __attribute__((aligned(16))) unsigned short bst[2 * KSTEPS * 64 * 8];
-  unsigned short* bhi = bst;
-  unsigned short* blo = bst + KSTEPS * 64 * 8;
-  __shared__ double s_mask[DP ? kMaxDet * kGemmPx : 1];
+  // B operand staging: [nb][hi, lo][kstep][lane][8], 16-bit
+  __shared__ __attribute__((aligned(16))) unsigned short bst[NB * 2 * KSTEPS * 64 * 8];
+  __shared__ double s_mask[DP ? kMaxDet * PX : 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -90,51 +92,65 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
   const int n_k = a.n_k;
   const int col = lane & 31;      // pixel of this lane in MFMA operands and results
   const int half = lane >> 5;
-  const int64_t kcol = (int64_t)tile * kGemmPx + col;
-  const bool cvalid = kcol < n_k;
   const int n_blocks = m_rows / 32;  // row blocks of this plan (energy window)
   const int n_om = a.n_om;
+  int64_t kcol[NB];
+  bool cvalid[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    kcol[nb] = (int64_t)tile * PX + kGemmPx * nb + col;
+    cvalid[nb] = kcol[nb] < n_k;
+  }
 
   if constexpr (DP) {
-    for (int i = tid; i < kMaxDet * kGemmPx; i += NT) {
-      const int d = i / kGemmPx, x = i % kGemmPx;
-      const int64_t kk = (int64_t)tile * kGemmPx + x;
+    for (int i = tid; i < kMaxDet * PX; i += NT) {
+      const int d = i / PX, x = i % PX;
+      const int64_t kk = (int64_t)tile * PX + x;
       s_mask[i] = (d < a.n_det && kk < n_k) ? a.masks[(int64_t)d * n_k + kk] : 0.0;
     }
   }
 
-  // staging role: thread handles pixel sp = tid % 32 and frame groups of 4
-  const int sp = tid & 31;
-  const int sgrp = tid >> 5;  // 0..15
-  const int64_t ks = (int64_t)tile * kGemmPx + sp;
+  // staging role: thread handles pixel sp of the tile and frame groups of 4
+  const int sp = tid % PX;
+  const int sgrp = tid / PX;
+  const int snb = sp / kGemmPx, s32 = sp % kGemmPx;
+  const int64_t ks = (int64_t)tile * PX + sp;
   const int64_t ksc = ks < n_k ? ks : (int64_t)n_k - 1;
 
-  double acc64[MBW][8];
+  double acc64[MBW][NB][8];
 #pragma unroll
   for (int b = 0; b < MBW; ++b)
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc64[b][q] = 0.0;
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc64[b][nb][q] = 0.0;
 
   for (int i = 0; i < a.n_probes; ++i) {
     const int p = a.probe0 + i;
     const double2 mu = a.cref[(int64_t)p * n_k + ksc];
     const float sc = gscale[(int64_t)p * n_k + ksc];
-    const float sc_col = gscale[(int64_t)p * n_k + (cvalid ? kcol : (int64_t)n_k - 1)];
-    const float inv2 = 1.0f / (sc_col * sc_col);
+    float inv2[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const float sc_col = gscale[(int64_t)p * n_k + (cvalid[nb] ? kcol[nb] : (int64_t)n_k - 1)];
+      inv2[nb] = 1.0f / (sc_col * sc_col);
+    }
     const InT* inb = (const InT*)a.in + (int64_t)i * a.pstride + pix_off(ksc, a.nx, a.row_stride);
 
     for (int s = a.s_lo; s < a.s_hi; ++s) {
       const int64_t seg0 = (int64_t)s * a.hop - a.push_begin;
-      f32x16 acc[MBW];
+      f32x16 acc[MBW][NB];
 #pragma unroll
       for (int b = 0; b < MBW; ++b)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) acc[b][v] = 0.0f;
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) acc[b][nb][v] = 0.0f;
 
       for (int c0 = 0; c0 < L; c0 += KC) {
-        __syncthreads();  // previous chunk's operand reads are complete
+        __syncthreads();  // previous stage's operand reads are complete
         // stage frames [c0, c0 + KC) of this chunk: groups of 4 frames per lane slot
-        for (int g4 = sgrp; g4 < KC / 4; g4 += NT / 32) {
+        for (int g4 = sgrp; g4 < KC / 4; g4 += SG) {
           const int t0 = c0 + 4 * g4;
           unsigned short hv[8], lv[8];
 #pragma unroll
@@ -145,9 +161,11 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
             split2<PREC>(yr, hv[2 * u], lv[2 * u]);
             split2<PREC>(yi, hv[2 * u + 1], lv[2 * u + 1]);
           }
-          const int tl = 4 * g4;                    // frame within the chunk
+          const int tl = 4 * g4;                    // frame within the stage
           const int kst = tl / 8, hh = (tl % 8) / 4;
-          const int slot = (kst * 64 + (sp + 32 * hh)) * 8;
+          const int lanep = s32 + 32 * hh;          // operand lane holding these 8 K values
+          const int hslot = (((snb * 2 + 0) * KSTEPS + kst) * 64 + lanep) * 8;
+          const int lslot = (((snb * 2 + 1) * KSTEPS + kst) * 64 + lanep) * 8;
           uint4 H, Lw;
           H.x = hv[0] | ((unsigned)hv[1] << 16);
           H.y = hv[2] | ((unsigned)hv[3] << 16);
@@ -157,13 +175,17 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
           Lw.y = lv[2] | ((unsigned)lv[3] << 16);
           Lw.z = lv[4] | ((unsigned)lv[5] << 16);
           Lw.w = lv[6] | ((unsigned)lv[7] << 16);
-          *reinterpret_cast<uint4*>(&bhi[slot]) = H;
-          *reinterpret_cast<uint4*>(&blo[slot]) = Lw;
+          *reinterpret_cast<uint4*>(&bst[hslot]) = H;
+          *reinterpret_cast<uint4*>(&bst[lslot]) = Lw;
         }
         __syncthreads();
         for (int kst = 0; kst < KSTEPS; ++kst) {
-          const h8 bh = *reinterpret_cast<const h8*>(&bhi[(kst * 64 + lane) * 8]);
-          const h8 bl = *reinterpret_cast<const h8*>(&blo[(kst * 64 + lane) * 8]);
+          h8 bh[NB], bl[NB];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            bh[nb] = *reinterpret_cast<const h8*>(&bst[(((nb * 2 + 0) * KSTEPS + kst) * 64 + lane) * 8]);
+            bl[nb] = *reinterpret_cast<const h8*>(&bst[(((nb * 2 + 1) * KSTEPS + kst) * 64 + lane) * 8]);
+          }
           const int kcol2 = 2 * c0 + 16 * kst + 8 * half;  // first of the lane's 8 K columns
 #pragma unroll
           for (int b = 0; b < MBW; ++b) {
@@ -172,9 +194,12 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
               const h8 ah = *reinterpret_cast<const h8*>(fmat + (int64_t)row * K2 + kcol2);
               const h8 al =
                   *reinterpret_cast<const h8*>(fmat + (int64_t)(m_rows + row) * K2 + kcol2);
-              acc[b] = mfma<PREC>(ah, bh, acc[b]);
-              acc[b] = mfma<PREC>(ah, bl, acc[b]);
-              acc[b] = mfma<PREC>(al, bh, acc[b]);
+#pragma unroll
+              for (int nb = 0; nb < NB; ++nb) {
+                acc[b][nb] = mfma<PREC>(ah, bh[nb], acc[b][nb]);
+                acc[b][nb] = mfma<PREC>(ah, bl[nb], acc[b][nb]);
+                acc[b][nb] = mfma<PREC>(al, bh[nb], acc[b][nb]);
+              }
             }
           }
         }
@@ -185,10 +210,13 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
       for (int b = 0; b < MBW; ++b) {
         if (wave + kGemmWaves * b < n_blocks) {
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const int v = 4 * (q / 2) + 2 * (q % 2);
-            const float pw = acc[b][v] * acc[b][v] + acc[b][v + 1] * acc[b][v + 1];
-            acc64[b][q] += (double)(pw * inv2);
+          for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int v = 4 * (q / 2) + 2 * (q % 2);
+              const float pw = acc[b][nb][v] * acc[b][nb][v] + acc[b][nb][v + 1] * acc[b][nb][v + 1];
+              acc64[b][nb][q] += (double)(pw * inv2[nb]);
+            }
           }
         }
       }
@@ -196,10 +224,11 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
 
     if constexpr (DP) {
       // cumulative detector partials through LDS, two halves of the rows
-      double* sd = reinterpret_cast<double*>(bst);  // needs L/2 * 32 doubles
-      static_assert(sizeof(bst) >= (size_t)L / 2 * kGemmPx * 8, "LDS for partials");
+      double* sd = reinterpret_cast<double*>(bst);
+      // n_om <= 128 MBW rows, so a half holds at most 64 MBW rows of PX pixels
+      static_assert(sizeof(bst) >= (size_t)64 * MBW * PX * 8, "LDS for partials");
       const int32_t* slots = a.pair_slot + (int64_t)tile * a.n_det;
-      const int hrows = (n_om + 1) / 2;  // <= L/2
+      const int hrows = (n_om + 1) / 2;
       for (int hb = 0; hb < 2; ++hb) {
         __syncthreads();
 #pragma unroll
@@ -208,8 +237,11 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
           for (int q = 0; q < 8; ++q) {
             const int rblk = wave + kGemmWaves * b;
             const int r = 16 * rblk + 4 * (q / 2) + 2 * half + (q % 2);
-            if (r < n_om && (r >= hrows) == (hb == 1))
-              sd[(r - hb * hrows) * kGemmPx + col] = acc64[b][q];
+            if (r < n_om && (r >= hrows) == (hb == 1)) {
+#pragma unroll
+              for (int nb = 0; nb < NB; ++nb)
+                sd[(r - hb * hrows) * PX + kGemmPx * nb + col] = acc64[b][nb][q];
+            }
           }
         }
         __syncthreads();
@@ -220,7 +252,7 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
             if (slot < 0) continue;
             double dsum = 0.0;
 #pragma unroll
-            for (int x = 0; x < kGemmPx; ++x) dsum += s_mask[d * kGemmPx + x] * sd[rr * kGemmPx + x];
+            for (int x = 0; x < PX; ++x) dsum += s_mask[d * PX + x] * sd[rr * PX + x];
             // cumulative over probes 0..i
             a.dpart[((int64_t)slot * a.n_probes + i) * n_om + r0 + rr] = dsum;
           }
@@ -229,32 +261,56 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
     }
   }
 
-  if (cvalid) {
 #pragma unroll
-    for (int b = 0; b < MBW; ++b) {
+  for (int b = 0; b < MBW; ++b) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int rblk = wave + kGemmWaves * b;
-        const int r = 16 * rblk + 4 * (q / 2) + 2 * half + (q % 2);
-        if (r < n_om) {
-          double* sp = a.S + (int64_t)r * n_k + kcol;
-          *sp = a.s_store ? acc64[b][q] : *sp + acc64[b][q];
+    for (int q = 0; q < 8; ++q) {
+      const int rblk = wave + kGemmWaves * b;
+      const int r = 16 * rblk + 4 * (q / 2) + 2 * half + (q % 2);
+      if (r < n_om) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          if (cvalid[nb]) {
+            double* sp = a.S + (int64_t)r * n_k + kcol[nb];
+            *sp = a.s_store ? acc64[b][nb][q] : *sp + acc64[b][nb][q];
+          }
         }
       }
     }
   }
 }
 
+// column blocks for a plan: the fewer 32-row blocks per wave, the more columns
+static int gemm_nb(int L, int n_om) {
+  const int mbw = (((2 * n_om + 31) / 32) + kGemmWaves - 1) / kGemmWaves;  // row blocks per wave
+  (void)L;
+  return mbw <= 1 ? 4 : (mbw == 2 ? 2 : 1);
+}
+
+template <int L, typename InT, int PREC, int MBW, int NB>
+static hipError_t launch_g4(const SegArgs& a, const void* fmat, int m_rows, const float* gscale,
+                            int n_tiles, hipStream_t st) {
+  if (a.n_det > 0)
+    hipLaunchKernelGGL((seg_gemm_kernel<L, InT, PREC, true, MBW, NB>), dim3(n_tiles),
+                       dim3(64 * kGemmWaves), 0, st, a, (const unsigned short*)fmat, m_rows, gscale);
+  else
+    hipLaunchKernelGGL((seg_gemm_kernel<L, InT, PREC, false, MBW, NB>), dim3(n_tiles),
+                       dim3(64 * kGemmWaves), 0, st, a, (const unsigned short*)fmat, m_rows, gscale);
+  return hipGetLastError();
+}
+
 template <int L, typename InT, int PREC>
 static hipError_t launch_g3(const SegArgs& a, const void* fmat, int m_rows, const float* gscale,
                             int n_tiles, hipStream_t st) {
-  if (a.n_det > 0)
-    hipLaunchKernelGGL((seg_gemm_kernel<L, InT, PREC, true>), dim3(n_tiles), dim3(64 * kGemmWaves),
-                       0, st, a, (const unsigned short*)fmat, m_rows, gscale);
-  else
-    hipLaunchKernelGGL((seg_gemm_kernel<L, InT, PREC, false>), dim3(n_tiles), dim3(64 * kGemmWaves),
-                       0, st, a, (const unsigned short*)fmat, m_rows, gscale);
-  return hipGetLastError();
+  const int nb = gemm_nb(L, a.n_om);
+  if (nb == 4) return launch_g4<L, InT, PREC, 1, 4>(a, fmat, m_rows, gscale, n_tiles, st);
+  if constexpr (L >= 256) {
+    if (nb == 2) return launch_g4<L, InT, PREC, 2, 2>(a, fmat, m_rows, gscale, n_tiles, st);
+  }
+  if constexpr (L >= 512) {
+    return launch_g4<L, InT, PREC, L / 128, 1>(a, fmat, m_rows, gscale, n_tiles, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int L>
@@ -270,7 +326,7 @@ static hipError_t launch_g2(int in_dtype, int prec, const SegArgs& a, const void
 }
 
 bool seg_gemm_supported(int L) { return L == 128 || L == 256 || L == 512; }
-int seg_gemm_tile_pixels(int) { return kGemmPx; }
+int seg_gemm_tile_pixels(int L, int n_om) { return kGemmPx * gemm_nb(L, n_om); }
 
 hipError_t launch_seg_gemm(int L, int in_dtype, bool /*sub64*/, int prec, const SegArgs& a,
                            const void* fmat, int m_rows, int n_tiles, hipStream_t st) {

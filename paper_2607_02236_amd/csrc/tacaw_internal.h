@@ -65,7 +65,7 @@ bool seg_fft_supported(int L);
 // output bins (row 2r + c), m_rows = 2 n_om rounded up to a multiple of 32
 hipError_t launch_seg_gemm(int L, int in_dtype, bool sub64, int prec, const SegArgs& a,
                            const void* fmat, int m_rows, int n_tiles, hipStream_t st);
-int seg_gemm_tile_pixels(int L);
+int seg_gemm_tile_pixels(int L, int n_om);  // pixels per workgroup for n_om output rows
 bool seg_gemm_supported(int L);
 hipError_t launch_gemm_scale(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
                              int32_t nx, int64_t rs, int64_t n_used, int32_t probe0,

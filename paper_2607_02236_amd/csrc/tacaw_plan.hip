@@ -470,7 +470,7 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   P->n_om = P->roi > 0 ? 2 * P->roi + 1 : P->L;
   P->m_rows = (2 * P->n_om + 31) / 32 * 32;
   const bool gemm = transform_is_gemm(d->transform);
-  P->W = gemm ? seg_gemm_tile_pixels(P->L) : seg_fft_tile_pixels(P->L);
+  P->W = gemm ? seg_gemm_tile_pixels(P->L, P->n_om) : seg_fft_tile_pixels(P->L);
   P->n_tiles = (P->n_k + P->W - 1) / P->W;
   P->cursor.assign(d->n_probe, 0);
   P->s_done.assign(d->n_probe, 0);
