@@ -33,9 +33,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_sha(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_sha(paths):
+    """sha256[:16] of the concatenated kernel sources (a path or a list of paths)."""
+    h = hashlib.sha256()
+    for path in [paths] if isinstance(paths, str) else paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profiles(kernel_src):
@@ -224,8 +228,9 @@ def main():
     n_seg = plan.info()["n_segments"]
     m_rows = (2 * n_om + 31) // 32 * 32  # GEMM rows computed (window rows, padded to 32)
     gemm_flops = 3 * 2 * m_rows * 2 * L * n_seg * spec.n_probe * spec.n_k  # executed, 3 products
-    ksrc = os.path.join(ROOT, "paper_2607_02236_amd", "csrc",
-                        "tacaw_fft.hip" if args.form == "fft" else "tacaw_gemm.hip")
+    csrc = os.path.join(ROOT, "paper_2607_02236_amd", "csrc")
+    ksrc = [os.path.join(csrc, f) for f in ("seg_fft_kernel.h", "regfft.h", "tacaw_fft.hip")] \
+        if args.form == "fft" else [os.path.join(csrc, "tacaw_gemm.hip")]
     out = {
         "metric": METRIC,
         "value": round(value, 2),

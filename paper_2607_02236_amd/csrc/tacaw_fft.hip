@@ -1,510 +1,24 @@
-// Fused chunk kernel, FFT form: ingest -> reference subtraction -> window ->
-// L-point FP32 FFT along time (two passes, one LDS exchange) -> |X|^2 -> FP64
-// accumulation over chunks and probes, plus the state of the exact elastic-mean
-// correction and per-probe detector partials.
-//
-// What is computed (paper Sec. II.B.2 and Eq. 1, 2): for chunk s of probe p and
-// pixel k, X'_s(m, k) = sum_t w(t) (psi(sH + t, k) - c(k)) exp(-2 pi i m t / L),
-// and S(m, k) += |X'_s(m, k)|^2. c is a per-(probe, pixel) reference (the first
-// frame, or the exact mean); the difference to the elastic mean mu is restored
-// exactly afterwards from FP64 sums (finalize), because for the supported
-// compact windows W(m) = sum_t w(t) exp(-2 pi i m t / L) vanishes outside bins
-// {0, 1, L-1}.
-//
-// Work decomposition (one workgroup = a tile of W adjacent pixels, all probes
-// and all chunks of the push):
-//   L = N1 * N2. Thread (px, n2) owns pixel k0 + px and the N1 samples
-//   t = N2 * n1 + n2; it loads them with lanes running along pixels (coalesced
-//   rows of W * 8 bytes), does the N1-point DFT over n1 in registers, applies
-//   the twiddle exp(-2 pi i n2 k1 / L), exchanges through LDS, and then as
-//   thread (px, j) does the N1 / N2 remaining N2-point DFTs over n2 for
-//   k1 = j + N2 q. Output bin m = k1 + N1 k2.
-//   With 50 % overlap (H = L/2) the second half of a chunk's samples (n1 >=
-//   N1/2) is the first half of the next chunk's, so every frame is read from
-//   memory once per push; other hops reload each chunk.
-#include <type_traits>
-
-#include "regfft.h"
-#include "tacaw_internal.h"
+// Launchers of the fused chunk kernel (push-buffer variants) and its shapes; the
+// kernel itself is in seg_fft_kernel.h, the ring-resident variant is launched from
+// tacaw_fft_ring.hip.
+#include "seg_fft_kernel.h"
 
 namespace tacaw {
-
-// Raw buffer load of one element at base + off (off < range, else 0): the base
-// and the range live in scalar registers, the offset in one VGPR.
-template <typename T>
-__device__ __forceinline__ T buffer_load(const char* base, uint32_t range, uint32_t off) {
-  __amdgpu_buffer_rsrc_t r =
-      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)range, 0x00020000);
-  if constexpr (sizeof(T) == 8) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
-  } else {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
-  }
-}
-
-template <int L>
-struct FftShape;
-template <>
-struct FftShape<64> {
-  static constexpr int N1 = 8, W = 16;
-};
-template <>
-struct FftShape<128> {
-  static constexpr int N1 = 16, W = 16;
-};
-template <>
-struct FftShape<256> {
-  static constexpr int N1 = 16, W = 16;
-};
-#ifndef TACAW_TILE_W512
-#define TACAW_TILE_W512 16  // pixels per workgroup at L = 512 (tuning parameter)
-#endif
-template <>
-struct FftShape<512> {
-  static constexpr int N1 = 16, W = TACAW_TILE_W512;
-};
-template <>
-struct FftShape<1024> {
-  static constexpr int N1 = 16, W = 8;
-};
-// L = 200 (the chunk length of the paper's worked example): 10-point DFTs
-// (prime-factor 2 x 5) in both passes; 32 pixels so that a wave's 64 lanes hold
-// two pass-2 roles of the same fold half
-template <>
-struct FftShape<200> {
-  static constexpr int N1 = 10, W = 32;
-};
-
-// Pass 2 for N2 > N1: the N2-point DFT of one k1 is shared by G = N2 / N1
-// threads. Thread g computes the outputs k2 = G r + g (r < N1) from
-//   y[n] = W_{N2}^{n g} sum_{j < G} A[n + N1 j] W_G^{j g},  X = DFT_{N1}(y),
-// i.e. one decimation-in-frequency stage folded into the loads, so no second
-// exchange is needed. G and g are compile-time here (g is uniform per wave).
-template <int N1, int G, int g>
-__device__ __forceinline__ void dif_combine(const float2* __restrict__ col, int stride,
-                                            float2 (&y)[N1]) {
-  constexpr int N2 = N1 * G;
-#pragma unroll
-  for (int n = 0; n < N1; ++n) {
-    float2 s = col[n * stride];
-#pragma unroll
-    for (int j = 1; j < G; ++j) {
-      const float2 x = col[(n + N1 * j) * stride];
-      // rotate by W_G^{j g} = exp(-2 pi i j g / G)
-      const int e = (j * g) % G;
-      float2 t;
-      if (G == 2) {
-        t = e == 0 ? x : make_float2(-x.x, -x.y);
-      } else {  // G == 4
-        t = e == 0 ? x : e == 1 ? make_float2(x.y, -x.x) : e == 2 ? make_float2(-x.x, -x.y)
-                                                           : make_float2(-x.y, x.x);
-      }
-      s.x += t.x;
-      s.y += t.y;
-    }
-    y[n] = s;
-  }
-  if constexpr (g != 0) {
-    TwiddleRow<N1, N2, g>::apply(y);
-  }
-}
-
-// LEAN: every chunk of the launch lies inside the push buffer and H = L/2, so
-// all loads use uniform row bases and the frames to count in the mean sum are
-// known per n1 at compile time. The general variant also reads the ring, takes
-// any hop and decides per lane.
-template <int L, typename InT, bool SUB64, bool DP, bool LEAN>
-__global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
-    seg_fft_kernel(const SegArgs a) {
-  constexpr int N1 = FftShape<L>::N1;
-  constexpr int W = FftShape<L>::W;
-  constexpr int N2 = L / N1;
-  constexpr int NT = W * N2;
-  constexpr int HALF = N1 / 2;
-  constexpr int ESZ = (int)sizeof(InT);
-  constexpr int BATCH = HALF;             // loads in flight per thread and batch
-  constexpr int R = N2 <= N1 ? N1 / N2 : 1;  // pass-2 DFTs per thread (N2 <= N1)
-  constexpr int G = N2 > N1 ? N2 / N1 : 1;   // threads per pass-2 DFT (N2 > N1)
-  constexpr int PADK = W;                  // LDS padding per k1 row (bank spread)
-  constexpr int KROW = N2 * W + PADK;      // float2 per k1 row of the exchange tile
-  static_assert(N1 % N2 == 0 || N2 % N1 == 0, "pass-2 split");
-  static_assert(G == 1 || G == 2 || G == 4, "pass-2 split factor");
-
-  // two exchange tiles [k1][n2][px] used by alternate chunks, so one barrier per
-  // chunk suffices; tile 0 is reused for the per-probe reductions
-  __shared__ float2 xbuf2[2 * N1 * KROW];
-  float2* const xbuf = xbuf2;
-  __shared__ float2 s_tw[L];          // [n2][k1]
-  __shared__ float s_win[L];          // [n2][n1]
-  __shared__ double s_mask[DP ? kMaxDet * W : 1];
-
-  const int tid = threadIdx.x;
-  const int px = tid % W;
-  const int n2 = tid / W;  // pass 1: time residue; pass 2: role j
-  const int tile = blockIdx.x;
-  const int n_k = a.n_k;
-  const int64_t k = (int64_t)tile * W + px;
-  const bool kvalid = k < n_k;
-  const int64_t kc = kvalid ? k : (int64_t)n_k - 1;
-
-  for (int i = tid; i < L; i += NT) {
-    s_tw[i] = a.tw[i];
-    s_win[i] = a.win_t[i];
-  }
-  if constexpr (DP) {
-    for (int i = tid; i < kMaxDet * W; i += NT) {
-      const int d = i / W, x = i % W;
-      const int64_t kk = (int64_t)tile * W + x;
-      s_mask[i] = (d < a.n_det && kk < n_k) ? a.masks[(int64_t)d * n_k + kk] : 0.0;
-    }
-  }
-  __syncthreads();
-
-  // pass-2 role: output bins owned by this thread are m = k1 + N1 k2 with
-  //   R-mode: k1 = j + N2 q (q < R), k2 = 0..N2-1         (acc index q*N2 + k2)
-  //   G-mode: k1 = j % N1, k2 = G r + g, g = j / N1      (acc index r)
-  const int j = n2;
-  const int k1g = j % N1;
-  const int gg = j / N1;  // uniform per wave (W * 4 lanes share it)
-
-  double acc[N1];  // FP64 sum of |X'|^2 over this launch's chunks and probes
-#pragma unroll
-  for (int i = 0; i < N1; ++i) acc[i] = 0.0;
-
-  const int H = a.hop;
-  const bool half_hop = (2 * H == L);
-  const bool track = a.track_mean != 0;
-  // correction bins: 0 -> thread j = 0 value 0; 1 -> j = 1 value 0; L-1 -> j = N2-1, last value
-  const int corr_b = (j == 0) ? 0 : (j == 1 ? 1 : 2);
-  const bool corr_own = track && (j == 0 || (a.n_corr == 3 && (j == 1 || j == N2 - 1)));
-  const int64_t row_bytes = a.fstride * ESZ;
-  // pixel kc inside an input frame (a k-space window may have wider pixel rows)
-  const int64_t kin = pix_off(kc, a.nx, a.row_stride);
-  // per-lane byte offset inside a frame row group: (n2 rows down, kc pixels across)
-  const uint32_t lane_off = (uint32_t)(((int64_t)n2 * a.fstride + kin) * ESZ);
-  // bytes addressable from a row-group base: N2 - 1 full frames plus the span of
-  // the last frame's pixels (the host checks that this fits in 32 bits)
-  const int64_t span = pix_off((int64_t)n_k - 1, a.nx, a.row_stride) + 1;
-  const uint32_t group_bytes = (uint32_t)((int64_t)(N2 - 1) * row_bytes + span * ESZ);
-
-  // LEAN: raw samples of the next chunk, loaded one chunk ahead (software prefetch)
-  InT pre[LEAN ? N1 : 1];
-  auto fetch_at = [&](int ii, int ss, int n1) -> InT {
-    const char* rb;
-    if (a.from_ring) {
-      // ring rows (ss H + N2 n1) mod D of probe probe0 + ii; D and H are multiples of
-      // N2, so a row group never wraps (row_bytes is one frame of the ring here)
-      int64_t row = ((int64_t)ss * H) % a.ring_depth + N2 * n1;
-      if (row >= a.ring_depth) row -= a.ring_depth;
-      const int64_t slot = (a.probe0 + ii) % a.n_slots;
-      rb = (const char*)a.ring + (slot * a.ring_depth + row) * row_bytes;
-    } else {
-      rb = (const char*)a.in + (int64_t)ii * a.pstride * ESZ +
-           ((int64_t)ss * H - a.push_begin + N2 * n1) * row_bytes;
-    }
-    return buffer_load<InT>(rb, group_bytes, lane_off);
-  };
-  if constexpr (LEAN) {
-#pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) pre[n1] = fetch_at(0, a.s_lo, n1);
-  }
-
-  int cc = 0;  // chunks processed by this thread block (selects the exchange tile)
-  for (int i = 0; i < a.n_probes; ++i) {
-    const int p = a.probe0 + i;
-    const double2 cr = a.cref[(int64_t)p * n_k + kc];
-    const float2 cf = make_float2((float)cr.x, (float)cr.y);
-    const char* in_probe = (const char*)a.in + (int64_t)i * a.pstride * ESZ;
-    const InT* ringb =
-        a.ring ? (const InT*)a.ring + ((int64_t)(p % a.n_slots) * a.ring_depth) * n_k + kc : nullptr;
-    double2 msum = make_double2(0.0, 0.0);
-    double2 xsum = make_double2(0.0, 0.0);
-    float2 kept[HALF];
-    bool have_kept = false;
-
-    for (int s = a.s_lo; s < a.s_hi; ++s) {
-      const int64_t seg0 = (int64_t)s * H;
-      const bool fast = LEAN || seg0 >= a.push_begin;
-      float2 v[N1];
-
-      // subtract the reference; add the frame to the FP64 mean sum when it is
-      // counted (each frame once, in the first chunk that contains it).
-      // CM: 0 = not tracked, 1 = every loaded frame counts, 2 = per-lane test
-      // t >= L - H, 3 = t >= L/2 (H = L/2), which is n1 >= N1/2 for every lane
-      auto take = [&](int n1, InT x, auto cmode) -> float2 {
-        constexpr int CM = decltype(cmode)::value;
-        const int tau = N2 * n1 + n2;
-        const bool count = CM == 1 || (CM == 2 && tau >= L - H) || (CM == 3 && n1 >= HALF);
-        float2 z;
-        double dx, dy;
-        if constexpr (SUB64) {
-          dx = (double)x.x - cr.x;
-          dy = (double)x.y - cr.y;
-          z = make_float2((float)dx, (float)dy);
-        } else {
-          z = make_float2((float)x.x - cf.x, (float)x.y - cf.y);
-          dx = (double)z.x;
-          dy = (double)z.y;
-        }
-        if constexpr (CM == 1) {
-          msum.x += dx;
-          msum.y += dy;
-        } else if constexpr (CM != 0) {
-          msum.x += count ? dx : 0.0;
-          msum.y += count ? dy : 0.0;
-        }
-        return z;
-      };
-      auto fetch_fast = [&](int n1) -> InT {
-        // uniform base of the row group N2 * n1 .. N2 * n1 + N2 - 1 of this chunk;
-        // one 32-bit lane offset (n2 rows, kc pixels) shared by every load
-        const char* rb = in_probe + (seg0 - a.push_begin + N2 * n1) * row_bytes;
-        return buffer_load<InT>(rb, group_bytes, lane_off);
-      };
-      auto fetch_any = [&](int n1) -> InT {
-        const int64_t f = seg0 + N2 * n1 + n2;
-        if (f >= a.push_begin)
-          return *(const InT*)(in_probe + (f - a.push_begin) * row_bytes + kin * ESZ);
-        return ringb[(f % a.ring_depth) * (int64_t)n_k];
-      };
-      auto load_range = [&](int lo, auto fetch, auto cmode) {
-#pragma unroll
-        for (int b0 = 0; b0 < N1; b0 += BATCH) {
-          if (b0 >= lo) {
-            InT raw[BATCH];
-#pragma unroll
-            for (int u = 0; u < BATCH; ++u) raw[u] = fetch(b0 + u);
-#pragma unroll
-            for (int u = 0; u < BATCH; ++u) v[b0 + u] = take(b0 + u, raw[u], cmode);
-          }
-        }
-      };
-      using C0 = std::integral_constant<int, 0>;
-      using C1 = std::integral_constant<int, 1>;
-      using C2 = std::integral_constant<int, 2>;
-      using C3 = std::integral_constant<int, 3>;
-
-      if constexpr (LEAN) {
-        // chunk s: frames with t >= L/2 (n1 >= HALF) are new; t < L/2 are new only for s = 0
-        auto take_pre = [&](int lo, auto cmode) {
-#pragma unroll
-          for (int n1 = 0; n1 < N1; ++n1)
-            if (n1 >= lo) v[n1] = take(n1, pre[n1], cmode);
-        };
-        if (have_kept) {
-#pragma unroll
-          for (int n1 = 0; n1 < HALF; ++n1) v[n1] = kept[n1];
-          if (track) take_pre(HALF, C1{});
-          else take_pre(HALF, C0{});
-        } else if (!track) {
-          take_pre(0, C0{});
-        } else if (s == 0) {
-          take_pre(0, C1{});
-        } else {
-          take_pre(0, C3{});
-        }
-        // prefetch the next chunk's new samples (or the next probe's first chunk)
-        if (s + 1 < a.s_hi) {
-#pragma unroll
-          for (int n1 = HALF; n1 < N1; ++n1) pre[n1] = fetch_at(i, s + 1, n1);
-        } else if (i + 1 < a.n_probes) {
-#pragma unroll
-          for (int n1 = 0; n1 < N1; ++n1) pre[n1] = fetch_at(i + 1, a.s_lo, n1);
-        }
-      } else if (have_kept && half_hop) {
-        // the kept half was counted in the previous chunk; the new half all counts
-#pragma unroll
-        for (int n1 = 0; n1 < HALF; ++n1) v[n1] = kept[n1];
-        if (fast) {
-          if (track) load_range(HALF, fetch_fast, C1{});
-          else load_range(HALF, fetch_fast, C0{});
-        } else {
-          if (track) load_range(HALF, fetch_any, C1{});
-          else load_range(HALF, fetch_any, C0{});
-        }
-      } else {
-        if (!track) {
-          if (fast) load_range(0, fetch_fast, C0{});
-          else load_range(0, fetch_any, C0{});
-        } else if (s == 0) {
-          if (fast) load_range(0, fetch_fast, C1{});
-          else load_range(0, fetch_any, C1{});
-        } else {
-          if (fast) load_range(0, fetch_fast, C2{});
-          else load_range(0, fetch_any, C2{});
-        }
-      }
-#pragma unroll
-      for (int n1 = HALF; n1 < N1; ++n1) kept[n1 - HALF] = v[n1];
-      have_kept = true;
-
-      // window (table stored per thread: s_win[n2 * N1 + n1] = w(N2 n1 + n2))
-#pragma unroll
-      for (int n1 = 0; n1 < N1; ++n1) {
-        const float w = s_win[n2 * N1 + n1];
-        v[n1].x *= w;
-        v[n1].y *= w;
-      }
-      // pass 1: DFT over n1, then twiddle exp(-2 pi i n2 k1 / L)
-      dft_inplace<N1>(v);
-#pragma unroll
-      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], s_tw[n2 * N1 + k1]);
-
-      // tile (cc & 1), cc counting this thread block's chunks: the reads of
-      // chunk cc - 2 from it finished before the barrier of chunk cc - 1, so only
-      // the barrier after the writes is needed
-      float2* const xb = xbuf2 + (cc & 1) * (N1 * KROW);
-      ++cc;
-#pragma unroll
-      for (int k1 = 0; k1 < N1; ++k1) xb[k1 * KROW + n2 * W + px] = v[k1];
-      __syncthreads();
-
-      if constexpr (G == 1) {
-        // R-mode: thread j transforms over n2 for k1 = j + N2 q
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-          float2 X[N2];
-          const float2* col = xb + (j + N2 * q) * KROW + px;
-#pragma unroll
-          for (int r = 0; r < N2; ++r) X[r] = col[r * W];
-          dft_inplace<N2>(X);
-#pragma unroll
-          for (int k2 = 0; k2 < N2; ++k2) {
-            const float pw = X[k2].x * X[k2].x + X[k2].y * X[k2].y;
-            acc[q * N2 + k2] += (double)pw;
-          }
-          if (corr_own) {
-            if (q == 0 && j <= 1) {
-              xsum.x += (double)X[0].x;
-              xsum.y += (double)X[0].y;
-            }
-            if (q == R - 1 && j == N2 - 1 && j > 1) {
-              xsum.x += (double)X[N2 - 1].x;
-              xsum.y += (double)X[N2 - 1].y;
-            }
-          }
-        }
-      } else {
-        // G-mode: G threads share the N2-point DFT of k1 = j % N1
-        const float2* col = xb + k1g * KROW + px;
-        float2 X[N1];
-        if constexpr (G == 2) {
-          if (gg == 0) dif_combine<N1, 2, 0>(col, W, X);
-          else dif_combine<N1, 2, 1>(col, W, X);
-        } else {
-          if (gg == 0) dif_combine<N1, 4, 0>(col, W, X);
-          else if (gg == 1) dif_combine<N1, 4, 1>(col, W, X);
-          else if (gg == 2) dif_combine<N1, 4, 2>(col, W, X);
-          else dif_combine<N1, 4, 3>(col, W, X);
-        }
-        dft_inplace<N1>(X);
-#pragma unroll
-        for (int r = 0; r < N1; ++r) {
-          const float pw = X[r].x * X[r].x + X[r].y * X[r].y;
-          acc[r] += (double)pw;
-        }
-        if (corr_own) {
-          if (j <= 1) {
-            xsum.x += (double)X[0].x;
-            xsum.y += (double)X[0].y;
-          } else {
-            xsum.x += (double)X[N1 - 1].x;
-            xsum.y += (double)X[N1 - 1].y;
-          }
-        }
-      }
-    }
-
-    if (track) {
-      __syncthreads();
-      double2* red = reinterpret_cast<double2*>(xbuf);
-      red[tid] = msum;
-      __syncthreads();
-      if (n2 == 0 && kvalid) {
-        double2 t = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int r = 0; r < N2; ++r) {
-          t.x += red[r * W + px].x;
-          t.y += red[r * W + px].y;
-        }
-        double2* ms = a.msum + (int64_t)p * n_k + k;
-        double2 o = *ms;
-        o.x += t.x;
-        o.y += t.y;
-        *ms = o;
-      }
-      if (corr_own && kvalid) {
-        double2* xp = a.xs + ((int64_t)p * kMaxCorr + corr_b) * n_k + k;
-        double2 o = *xp;
-        o.x += xsum.x;
-        o.y += xsum.y;
-        *xp = o;
-      }
-    }
-
-    if constexpr (DP) {
-      // detector partials: the mask-weighted tile sum of the FP64 accumulator,
-      // cumulative over this launch's probes (the reduce kernel differences them)
-      __syncthreads();
-      double* sp = reinterpret_cast<double*>(xbuf);  // [L][W]
-#pragma unroll
-      for (int t = 0; t < N1; ++t) {
-        const int m = (G == 1) ? (j + N2 * (t / N2)) + N1 * (t % N2) : k1g + N1 * (G * t + gg);
-        sp[m * W + px] = acc[t];
-      }
-      __syncthreads();
-      const int n_om = a.n_om;
-      const int32_t* slots = a.pair_slot + (int64_t)tile * a.n_det;
-      for (int r = tid; r < n_om; r += NT) {
-        int m = r - a.roi_half;  // output row r holds bin m
-        if (m < 0) m += L;
-        double pv[W];
-#pragma unroll
-        for (int x = 0; x < W; ++x) pv[x] = sp[m * W + x];
-#pragma unroll 1
-        for (int d = 0; d < a.n_det; ++d) {
-          const int slot = slots[d];  // uniform; -1: this detector's mask is zero here
-          if (slot < 0) continue;
-          double dsum = 0.0;
-#pragma unroll
-          for (int x = 0; x < W; ++x) dsum += s_mask[d * W + x] * pv[x];
-          // cumulative over the launch's probes 0..i
-          a.dpart[((int64_t)slot * a.n_probes + i) * n_om + r] = dsum;
-        }
-      }
-    }
-    // the reductions above used tile 0, which a later chunk writes
-    __syncthreads();
-  }
-
-  if (kvalid) {
-#pragma unroll
-    for (int t = 0; t < N1; ++t) {
-      const int m = (G == 1) ? (j + N2 * (t / N2)) + N1 * (t % N2) : k1g + N1 * (G * t + gg);
-      int row = m + a.roi_half;  // rows >= n_om lie outside the energy window
-      if (row >= L) row -= L;
-      if (row < a.n_om) {
-        double* sp = a.S + (int64_t)row * n_k + k;
-        *sp = a.s_store ? acc[t] : *sp + acc[t];
-      }
-    }
-  }
-}
 
 template <int L, typename InT, bool SUB64>
 static hipError_t launch_t(const SegArgs& a, int n_tiles, hipStream_t st) {
   constexpr int NT = FftShape<L>::W * (L / FftShape<L>::N1);
-  const bool lean = (2 * a.hop == L) && (a.from_ring || (int64_t)a.s_lo * a.hop >= a.push_begin);
+  const bool lean = (2 * a.hop == L) && !a.from_ring && (int64_t)a.s_lo * a.hop >= a.push_begin;
   if (lean) {
     if (a.n_det > 0)
-      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, true>), dim3(n_tiles), dim3(NT), 0, st, a);
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, 1>), dim3(n_tiles), dim3(NT), 0, st, a);
     else
-      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, false, true>), dim3(n_tiles), dim3(NT), 0, st, a);
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, false, 1>), dim3(n_tiles), dim3(NT), 0, st, a);
   } else {
     if (a.n_det > 0)
-      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, false>), dim3(n_tiles), dim3(NT), 0, st, a);
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, 0>), dim3(n_tiles), dim3(NT), 0, st, a);
     else
-      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, false, false>), dim3(n_tiles), dim3(NT), 0, st, a);
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, false, 0>), dim3(n_tiles), dim3(NT), 0, st, a);
   }
   return hipGetLastError();
 }
@@ -549,6 +63,7 @@ int seg_fft_tile_pixels(int L) {
 
 hipError_t launch_seg_fft(int L, int in_dtype, bool sub64, const SegArgs& a, int n_tiles,
                           hipStream_t st) {
+  if (a.from_ring && 2 * a.hop == L) return launch_seg_fft_ring(L, in_dtype, sub64, a, n_tiles, st);
   switch (L) {
     case 64: return launch_l<64>(in_dtype, sub64, a, n_tiles, st);
     case 128: return launch_l<128>(in_dtype, sub64, a, n_tiles, st);

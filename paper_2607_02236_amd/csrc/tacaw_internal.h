@@ -57,6 +57,9 @@ struct SegArgs {
 // Launchers (return hipError_t of the launch).
 hipError_t launch_seg_fft(int L, int in_dtype, bool sub64, const SegArgs& a, int n_tiles,
                           hipStream_t st);
+// the whole-series variant reading every frame from the ring (a.from_ring, 2 hop = L)
+hipError_t launch_seg_fft_ring(int L, int in_dtype, bool sub64, const SegArgs& a, int n_tiles,
+                               hipStream_t st);
 int seg_fft_tile_pixels(int L);
 void seg_fft_split(int L, int* n1, int* n2);  // L = N1 * N2 of the push kernel's tables
 bool seg_fft_supported(int L);

@@ -330,13 +330,18 @@ def test_leakage_tails_pointwise(tacaw, window):
     w = O.window("hann", L) if window == "hann" else scipy.signal.get_window(window, L)
     g = run_gpu(tacaw, psi, L, L, window=window if window == "hann" else w)
     So, _ = O.tacaw_spectra(psi.numpy(), L, L, w)
+    # Hann tails have no zeros at half-integer offsets: compare bin by bin. The
+    # Blackman-Harris transform passes near zero between its -92 dB sidelobes, so
+    # there the error is measured against the tone's peak (dB below the peak).
     worst = 0.0
     for k in range(ny * nx):
+        peak = So[:, k].max()
         for d in np.arange(4.5, 33.0, 1.0):
             m = int(nu[k] + d) % L
-            worst = max(worst, abs(g["S"][m, k] - So[m, k]) / So[m, k])
-    say(f"{window} tails: worst pointwise rel err {worst:.2e}")
-    assert worst <= 1e-2
+            err = abs(g["S"][m, k] - So[m, k])
+            worst = max(worst, err / So[m, k] if window == "hann" else err / peak)
+    say(f"{window} tails: worst {'pointwise rel' if window == 'hann' else 'rel to peak'} err {worst:.2e}")
+    assert worst <= (1e-2 if window == "hann" else 1e-10)
 
 
 @pytest.mark.parametrize("L,H,NT,D,pushes", [
