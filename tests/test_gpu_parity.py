@@ -32,9 +32,10 @@ def tacaw():
 
 
 def rel(a, b):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    # relative L2 error; complex arrays keep their imaginary parts
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
 def run_gpu(tacaw, psi, L, H, masks=None, pushes=None, probe_batches=None, **kw):
