@@ -44,6 +44,20 @@ __device__ __forceinline__ T buffer_load(const char* base, uint32_t range, uint3
   }
 }
 
+// The same with a scalar offset: element at base + soffset + off, range counted
+// from base (one descriptor serves several row groups).
+template <typename T>
+__device__ __forceinline__ T buffer_load_so(const char* base, uint32_t range, uint32_t off,
+                                            uint32_t soff) {
+  __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)range, 0x00020000);
+  if constexpr (sizeof(T) == 8) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, (int)soff, 0));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, (int)soff, 0));
+  }
+}
+
 template <int L>
 struct FftShape;
 template <>
@@ -117,12 +131,15 @@ __device__ __forceinline__ void dif_combine(const float2* __restrict__ col, int 
 // any hop and decides per lane.
 // MODE 0: general (any hop; frames before the push from the ring, per lane);
 // MODE 1: whole-series variant reading the push buffer; MODE 2: whole-series
-// variant reading every frame from the ring (deferred streaming).
+// variant reading every frame from the ring (deferred streaming); MODE 3: MODE 1
+// when a whole chunk of frames spans less than 2 GiB, so one buffer descriptor per
+// chunk serves all row groups through a scalar offset (fewer scalar registers).
 template <int L, typename InT, bool SUB64, bool DP, int MODE>
 __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
     seg_fft_kernel(const SegArgs a) {
   constexpr bool LEAN = MODE != 0;
   constexpr bool RING = MODE == 2;
+  constexpr bool NARROW = MODE == 3;
   constexpr int N1 = FftShape<L>::N1;
   constexpr int W = FftShape<L>::W;
   constexpr int N2 = L / N1;
@@ -196,9 +213,16 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
 
   // LEAN: raw samples of the next chunk, loaded one chunk ahead (software prefetch)
   InT pre[LEAN ? N1 : 1];
+  // MODE 3: a chunk's frames lie within 2 GiB of its first row
+  const uint32_t chunk_bytes =
+      NARROW ? (uint32_t)((int64_t)(L - N2) * row_bytes + (int64_t)group_bytes) : 0u;
   auto fetch_at = [&](int ii, int ss, int n1) -> InT {
     const char* rb;
-    if constexpr (RING) {
+    if constexpr (NARROW) {
+      const char* cb = (const char*)a.in + (int64_t)ii * a.pstride * ESZ +
+                       ((int64_t)ss * H - a.push_begin) * row_bytes;
+      return buffer_load_so<InT>(cb, chunk_bytes, lane_off, (uint32_t)(N2 * n1 * row_bytes));
+    } else if constexpr (RING) {
       // ring rows (ss H + N2 n1) mod D of probe probe0 + ii; D and H are multiples of
       // N2, so a row group never wraps (row_bytes is one frame of the ring here)
       int64_t row = ((int64_t)ss * H) % a.ring_depth + N2 * n1;

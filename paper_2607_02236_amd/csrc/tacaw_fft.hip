@@ -9,7 +9,16 @@ template <int L, typename InT, bool SUB64>
 static hipError_t launch_t(const SegArgs& a, int n_tiles, hipStream_t st) {
   constexpr int NT = FftShape<L>::W * (L / FftShape<L>::N1);
   const bool lean = (2 * a.hop == L) && !a.from_ring && (int64_t)a.s_lo * a.hop >= a.push_begin;
-  if (lean) {
+  // one descriptor per chunk when a chunk's frames span less than 2 GiB
+  const int64_t span = pix_off((int64_t)a.n_k - 1, a.nx, a.row_stride) + 1;
+  const bool narrow =
+      ((int64_t)(L - 1) * a.fstride + span) * (int64_t)sizeof(InT) < ((int64_t)1 << 31);
+  if (lean && narrow) {
+    if (a.n_det > 0)
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, 3>), dim3(n_tiles), dim3(NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, false, 3>), dim3(n_tiles), dim3(NT), 0, st, a);
+  } else if (lean) {
     if (a.n_det > 0)
       hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, 1>), dim3(n_tiles), dim3(NT), 0, st, a);
     else

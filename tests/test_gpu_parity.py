@@ -418,3 +418,24 @@ def test_k_space_window_adjoint(tacaw):
         outs.append(g[:, :, :, :].contiguous().cpu().numpy())
         plan.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_chunks_spanning_more_than_2_gib(tacaw):
+    # frames 32 MiB apart (a small image inside a large frame stride): a chunk of 128
+    # frames spans 4 GiB, which takes the per-row-group descriptor variant; results
+    # equal the contiguous layout
+    spec = T.SeriesSpec(2, 640, 8, 8, dtype="c64", seed=88, model="lines", n_terms=8)
+    psi = T.generate(spec)
+    masks = T.standard_masks(8, 8, scale=0.05)
+    ref = run_gpu(tacaw, psi, 128, 64, masks)
+    fs = (1 << 22) + 64  # elements per frame
+    big = torch.empty((2, 640, fs), dtype=torch.complex64, device="cuda")
+    view = big[:, :, :64].view(2, 640, 8, 8)
+    view.copy_(psi.cuda())
+    plan = tacaw.Plan(2, 8, 8, 640, 128, 64, masks=torch.from_numpy(masks).cuda())
+    plan.push(view)
+    S = plan.finalize().cpu().numpy().reshape(128, -1)
+    _, Dp = plan.detector_spectra(per_probe=True)
+    plan.close()
+    del big
+    assert rel(S, ref["S"]) < 1e-12 and rel(Dp.cpu().numpy(), ref["Dp"]) < 1e-12
