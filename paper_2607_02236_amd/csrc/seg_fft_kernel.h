@@ -225,13 +225,24 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
     } else if constexpr (RING) {
       // ring rows (ss H + N2 n1) mod D of probe probe0 + ii; D and H are multiples of
       // N2, so a row group never wraps (row_bytes is one frame of the ring here)
-      int64_t row = ((int64_t)ss * H) % a.ring_depth + N2 * n1;
-      if (row >= a.ring_depth) row -= a.ring_depth;
+      // the chunks of one launch span at most D frames, so from the first chunk's row
+      // (ring_row_lo, from the host) each chunk and row group wraps at most once
+      const int D = (int)a.ring_depth;
+      int row = a.ring_row_lo + (ss - a.s_lo) * H;
+      if (row >= D) row -= D;
+      row += N2 * n1;
+      if (row >= D) row -= D;
       const int64_t slot = (a.probe0 + ii) % a.n_slots;
-      rb = (const char*)a.ring + (slot * a.ring_depth + row) * row_bytes;
+      int64_t rbytes = row_bytes;  // formed next to the load (see the push case below)
+      asm volatile("" : "+s"(rbytes));
+      rb = (const char*)a.ring + (slot * D + row) * rbytes;
     } else {
+      // the row-group stride passes through an empty asm so that the 16 per-group
+      // offsets are formed next to each load instead of being kept (and spilled)
+      int64_t gstride = (int64_t)N2 * row_bytes;
+      asm volatile("" : "+s"(gstride));
       rb = (const char*)a.in + (int64_t)ii * a.pstride * ESZ +
-           ((int64_t)ss * H - a.push_begin + N2 * n1) * row_bytes;
+           ((int64_t)ss * H - a.push_begin) * row_bytes + n1 * gstride;
     }
     return buffer_load<InT>(rb, group_bytes, lane_off);
   };
@@ -289,7 +300,9 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
       auto fetch_fast = [&](int n1) -> InT {
         // uniform base of the row group N2 * n1 .. N2 * n1 + N2 - 1 of this chunk;
         // one 32-bit lane offset (n2 rows, kc pixels) shared by every load
-        const char* rb = in_probe + (seg0 - a.push_begin + N2 * n1) * row_bytes;
+        int64_t gstride = (int64_t)N2 * row_bytes;  // formed next to the load (see fetch_at)
+        asm volatile("" : "+s"(gstride));
+        const char* rb = in_probe + (seg0 - a.push_begin) * row_bytes + n1 * gstride;
         return buffer_load<InT>(rb, group_bytes, lane_off);
       };
       auto fetch_any = [&](int n1) -> InT {

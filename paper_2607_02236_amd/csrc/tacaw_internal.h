@@ -27,7 +27,8 @@ struct SegArgs {
   int64_t push_begin;      // absolute frame index of the push buffer's frame 0
   const void* ring;        // [n_slots][D][n_k] frames pushed earlier, slot = probe % n_slots,
                            // frame f at row f mod D
-  int64_t ring_depth;      // D (>= L)
+  int64_t ring_depth;      // D (>= L, < 2^30)
+  int32_t ring_row_lo;     // (s_lo * hop) mod D: ring row of the launch's first chunk
   int32_t from_ring;       // whole-series variant: every chunk is read from the ring
   int32_t n_slots;
   int32_t n_k;

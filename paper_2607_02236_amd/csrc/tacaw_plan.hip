@@ -274,6 +274,7 @@ static int run_chunks(tacaw_plan_t P, const void* src, int64_t pstride, int64_t 
   g.push_begin = from_ring ? ((int64_t)1 << 62) : push_begin;
   g.ring = P->ring;
   g.ring_depth = P->D;
+  g.ring_row_lo = (int32_t)(((int64_t)s_lo * P->H) % P->D);
   g.from_ring = from_ring ? 1 : 0;
   g.n_slots = P->n_slots;
   g.n_k = P->n_k;
@@ -438,9 +439,10 @@ int tacaw_plan_check(const tacaw_plan_desc* d) {
   if (d->k_row_stride != 0 && d->k_row_stride < d->nx)
     return fail(TACAW_ERR_INVALID_ARG, "k_row_stride must be 0 or >= nx");
   if (d->ring_frames != 0) {
-    if (d->ring_frames <= d->seg_len || d->ring_frames % (d->seg_len / 2) != 0)
+    if (d->ring_frames <= d->seg_len || d->ring_frames % (d->seg_len / 2) != 0 ||
+        d->ring_frames >= ((int64_t)1 << 30))
       return fail(TACAW_ERR_INVALID_ARG,
-                  "ring_frames must be 0 or a multiple of seg_len/2 larger than seg_len");
+                  "ring_frames must be 0 or a multiple of seg_len/2 in (seg_len, 2^30)");
     if (d->transform != TACAW_FFT_F32)
       return fail(TACAW_ERR_UNSUPPORTED, "deferred ring mode needs the FFT transform");
   }
