@@ -12,6 +12,10 @@ pixels, complex64 (68.7 GB of exit waves); Welch chunks of L = 512 with 50 %
 overlap, periodic Hann; 4 detector masks. Metric: exit-wave GB/s (unique
 exit-wave bytes / step time).
 
+Workload "gradient": 16 probes x 1024 frames x 128 x 128 complex64, L = H =
+512, width-r Hann at r = 1, 4 masks; one step is the forward pass above plus
+the adjoint (dL/dpsi and dL/dr for L = sum_j sum_m a_j(m) D_j(m)).
+
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 
@@ -57,9 +61,10 @@ def traffic_from_profiles(kernel_src):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(spec, L, H, n_pix, seed=0):
+def cpu_baseline(spec, L, H, n_pix, seed=0, gradient=False):
     """The FP64 oracle (brute-force DFT) on all probes and frames of a seeded
-    subset of pixels; returns exit-wave GB/s in the metric's unit."""
+    subset of pixels (with gradient: the forward and its vector-Jacobian product
+    for the detector loss); returns exit-wave GB/s in the metric's unit."""
     import numpy as np
     import torch
 
@@ -75,13 +80,18 @@ def cpu_baseline(spec, L, H, n_pix, seed=0):
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         cores = os.cpu_count() or 1
-    w = O.window("hann", L)
+    w = O.window("hann_width" if gradient else "hann", L, 1.0)
     t0 = time.perf_counter()
     O.tacaw_spectra(psi, L, H, w)
+    if gradient:
+        masks = T.standard_masks(spec.ny, spec.nx, scale=spec.ny / 256).reshape(4, -1)[:, pix]
+        gS = np.einsum("jm,jk->mk", T.loss_weights(4, L, seed=4), masks)
+        O.spectra_vjp(psi, L, H, w, gS, dw=O.window_width_derivative(L, 1.0))
     dt = time.perf_counter() - t0
     nbytes = psi.shape[0] * psi.shape[1] * n_pix * 8
     return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"brute-force FP64 DFT oracle on all {psi.shape[0]} probes x "
+            "sample": ("forward + adjoint of the " if gradient else "")
+                      + f"brute-force FP64 DFT oracle on all {psi.shape[0]} probes x "
                       f"{psi.shape[1]} frames of {n_pix} seeded pixels ({dt:.1f} s)"}
 
 
@@ -96,11 +106,13 @@ def main():
     ap.add_argument("--seg-len", type=int, default=512)
     ap.add_argument("--form", default="fft", choices=["fft", "gemm_bf16x3", "gemm_f16x3"])
     ap.add_argument("--workload", default="realistic",
-                    choices=["realistic", "precision", "streaming"],
+                    choices=["realistic", "precision", "streaming", "gradient"],
                     help="realistic: 64 probes x 2048 frames x 256^2 c64 (default); precision: "
                          "1 probe x 512 frames x 64^2 c128, one chunk of 512; streaming: "
                          "--probes (default 16) x 4096 frames x 1024^2 c64, L=1024 H=512, "
-                         "pushed in pieces of --push-frames frames through the plan's ring")
+                         "pushed in pieces of --push-frames frames through the plan's ring; "
+                         "gradient: 16 probes x 1024 frames x 128^2 c64, L=H=512, forward + "
+                         "adjoint")
     ap.add_argument("--push-frames", type=int, default=256)
     ap.add_argument("--ring-frames", type=int, default=0,
                     help="streaming: deferred ring depth per probe (0: chunks run in the push "
@@ -132,6 +144,9 @@ def main():
     if args.workload == "precision":
         L, H = 512, 512
         spec = T.config_precision(n_frames=512)
+    elif args.workload == "gradient":
+        L, H = 512, 512
+        spec = T.config_gradient()
     elif args.workload == "streaming":
         L, H = 1024, 512
         n_pr = args.probes if args.probes != 64 else 16
@@ -168,6 +183,7 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: {n * 4} bytes read and written per copy")
         del src, dst
+    gradient = args.workload == "gradient"
     masks = torch.from_numpy(T.standard_masks(spec.ny, spec.nx, scale=spec.ny / 256)).cuda()
     if args.workload == "precision":
         masks = torch.from_numpy(np.stack([T.disk_mask(64, 64, 24, inner=8),
@@ -177,9 +193,11 @@ def main():
 
     dt_fs = 5.0
     M = axes.omega_half_for(L, dt_fs, e_max_mev=args.roi_mev) if args.roi_mev > 0 else 0
+    win = dict(window="hann_width", window_param=1.0) if gradient else {}
     plan = tacaw.Plan(spec.n_probe, spec.ny, spec.nx, spec.n_frames, L, H, masks=masks,
                       transform=args.form, in_dtype=spec.dtype, time_kernels=True, stream=stream,
-                      dt_fs=dt_fs, omega_half=M, ring_frames=args.ring_frames if streaming else 0)
+                      dt_fs=dt_fs, omega_half=M, ring_frames=args.ring_frames if streaming else 0,
+                      **win)
     R = psi.shape[1]
     pieces = [(f0, min(spec.n_frames, f0 + args.push_frames))
               for f0 in range(0, spec.n_frames, args.push_frames)] if streaming else [(0, spec.n_frames)]
@@ -187,6 +205,13 @@ def main():
     S = torch.empty((n_om, spec.ny, spec.nx), dtype=torch.float64, device="cuda")
     D = torch.empty((masks.shape[0], n_om), dtype=torch.float64, device="cuda")
     Dp = torch.empty((masks.shape[0], spec.n_probe, n_om), dtype=torch.float64, device="cuda")
+    if gradient:  # loss sum_j sum_m a_j(m) D_j(m): dLoss/dD = a
+        gD = torch.from_numpy(T.loss_weights(masks.shape[0], n_om, seed=4)).cuda()
+        grad = torch.empty_like(psi)
+        gw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    bwd_ms = []
+    b0 = torch.cuda.Event(enable_timing=True)
+    b1 = torch.cuda.Event(enable_timing=True)
 
     def step(measure=False):
         plan.reset()
@@ -198,6 +223,11 @@ def main():
                 k_ms += t if t > 0 else 0.0  # -1: this push completed no chunk
         plan.finalize(S)
         plan.detector_spectra(per_probe=True, out=D, out_p=Dp)
+        if gradient:
+            gw.zero_()
+            b0.record(stream)
+            plan.backward(psi, gD=gD, grad=grad, grad_wparam=gw)
+            b1.record(stream)
         return k_ms
 
     for i in range(args.warmup):
@@ -213,6 +243,9 @@ def main():
         step()
         if not streaming:  # waits for this step's chunk kernel
             kernel_ms.append(plan.info()["last_chunk_kernel_ms"])
+        if gradient:  # the adjoint's kernels (the plan's stream is this stream)
+            b1.synchronize()
+            bwd_ms.append(b0.elapsed_time(b1))
     e1.record(stream)
     torch.cuda.synchronize()
     if streaming:  # one more (untimed) step that reads the kernel time after every push
@@ -247,8 +280,9 @@ def main():
                 + (f"; frames repeat with period {R} (resident block)" if R < spec.n_frames else ""),
         "config": {
             "workload": f"{spec.n_probe} probes x {spec.n_frames} frames x {spec.ny}x{spec.nx} {spec.dtype}, "
-                        f"Welch L={L} H={H} periodic Hann, global mean, {masks.shape[0]} detector masks, "
-                        f"transform {args.form}"
+                        f"Welch L={L} H={H} " + ("width-r Hann r=1" if gradient else "periodic Hann")
+                        + f", global mean, {masks.shape[0]} detector masks, transform {args.form}"
+                        + (", forward + adjoint (dL/dpsi and dL/dr of sum_j a_j . D_j)" if gradient else "")
                         + (f", pushed in pieces of {args.push_frames} frames" if streaming else "")
                         + (f", deferred ring of {args.ring_frames} frames" if streaming and args.ring_frames else "")
                         + (f", energy window |E| <= {args.roi_mev:g} meV ({n_om} bins)" if M else ""),
@@ -269,6 +303,18 @@ def main():
                     "per element at 50% overlap; 39.3 T lane-ops/s peak), not by HBM",
         },
     }
+    if gradient:
+        t_b = float(np.mean(bwd_ms))
+        ach_b = 2 * b_alg / (t_b * 1e-3) / 1e9
+        out["roofline"] = {
+            "bound": "hbm", "kernel": "bwd_kernel", "achieved": round(ach_b, 2),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach_b / HBM_PEAK_GBS, 4),
+            "kernel_ms": round(t_b, 4), "traffic": None,
+            "forward_chunk_kernel_ms": round(k_ms, 4),
+            "note": "adjoint launch (bwd_kernel and the window-parameter reduction): reads "
+                    "psi once and writes dL/dpsi once (2 x exit-wave bytes); it recomputes "
+                    "each chunk's transform and runs a second one, so it is VALU-bound",
+        }
     if args.form != "fft":
         tf = gemm_flops / (k_ms * 1e-3) / 1e12
         out["dtype"] = "f16x3" if args.form == "gemm_f16x3" else "bf16x3"
@@ -283,7 +329,8 @@ def main():
         log("timing the CPU oracle on a bounded sample")
         del psi
         torch.cuda.empty_cache()
-        out["cpu_baseline"] = cpu_baseline(spec, L, H, args.cpu_pixels)
+        out["cpu_baseline"] = cpu_baseline(spec, L, H, args.cpu_pixels if not gradient else 8192,
+                                           gradient=gradient)
     plan.close()
     print(json.dumps(out), flush=True)
 

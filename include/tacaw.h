@@ -218,7 +218,10 @@ int tacaw_detector_spectra(tacaw_plan_t plan, const double* d_masks_or_null, int
  * (dLoss/dD_j, plan masks), d_gDp [n_det][n_probe][n_omega] (dLoss/dD_{j,p}).
  * d_frames: the complete series of probes [probe0, probe0 + n_probes) again
  * (same layout rules as tacaw_push_frames, all frames_used frames present);
- * chunk transforms are recomputed, not stored. d_grad_frames: output, same
+ * chunk transforms are recomputed, not stored. The elastic mean, and for
+ * windows whose DFT lives on bins 0 and +-1 the mean term of the gradient, are
+ * taken from the forward pass's FP64 sums, so d_frames must hold the frames
+ * that were pushed. d_grad_frames: output, same
  * dtype and strides as d_frames, d/dRe + i d/dIm convention; it is fully
  * written for frames < frames_used and left untouched beyond. d_grad_wparam:
  * device float64 scalar that receives (+=) dLoss/d(window_param) for

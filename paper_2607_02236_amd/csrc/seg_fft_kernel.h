@@ -79,9 +79,12 @@ template <>
 struct FftShape<512> {
   static constexpr int N1 = 16, W = TACAW_TILE_W512;
 };
+#ifndef TACAW_TILE_W1024
+#define TACAW_TILE_W1024 8  // pixels per workgroup at L = 1024 (tuning parameter)
+#endif
 template <>
 struct FftShape<1024> {
-  static constexpr int N1 = 16, W = 8;
+  static constexpr int N1 = 16, W = TACAW_TILE_W1024;
 };
 // L = 200 (the chunk length of the paper's worked example): 10-point DFTs
 // (prime-factor 2 x 5) in both passes; 32 pixels so that a wave's 64 lanes hold
@@ -165,7 +168,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
   const int tid = threadIdx.x;
   const int px = tid % W;
   const int n2 = tid / W;  // pass 1: time residue; pass 2: role j
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile();
   const int n_k = a.n_k;
   const int64_t k = (int64_t)tile * W + px;
   const bool kvalid = k < n_k;
@@ -348,12 +351,13 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
           take_pre(0, C3{});
         }
         // prefetch the next chunk's new samples (or the next probe's first chunk)
-        if (s + 1 < a.s_hi) {
+        const bool next_chunk = s + 1 < a.s_hi;
+        if (next_chunk || i + 1 < a.n_probes) {
+          const int ii = next_chunk ? i : i + 1;
+          const int ss = next_chunk ? s + 1 : a.s_lo;
 #pragma unroll
-          for (int n1 = HALF; n1 < N1; ++n1) pre[n1] = fetch_at(i, s + 1, n1);
-        } else if (i + 1 < a.n_probes) {
-#pragma unroll
-          for (int n1 = 0; n1 < N1; ++n1) pre[n1] = fetch_at(i + 1, a.s_lo, n1);
+          for (int n1 = 0; n1 < N1; ++n1)
+            if (n1 >= HALF || !next_chunk) pre[n1] = fetch_at(ii, ss, n1);
         }
       } else if (have_kept && half_hop) {
         // the kept half was counted in the previous chunk; the new half all counts

@@ -6,10 +6,19 @@
 //   g_z(t)  = w(t) g_y(t)
 //   grad psi(n) = sum over the chunks holding n of g_z(n - sH)
 //                 - [n < N_used] (1 / N_used) sum_s sum_t g_z_s(t)   (GLOBAL mean)
+// The mean-term sum is sum_s sum_m 2 G(m) X_s(m) conj(W(m)), W the window's DFT.
+// For a window whose W vanishes outside bins {0, 1, L-1} it needs only the FP64
+// chunk sums of X at those bins, which the forward pass kept for its exact mean
+// correction (sum_s X_s = sum_s X'_s - N_s delta W, delta = mu - c); the term is
+// then subtracted as each frame is stored. Otherwise the sum is accumulated here
+// and a second pass subtracts it. mu = c + (FP64 sum of psi - c) / N_used, also
+// from the forward pass.
 //   dLval/dr = sum Re[conj(g_y) z] dw/dr - 2 Lval sum_t w dw/dr / sum_t w^2
 // with G_p(m,k) = kappa_S (gS(m,k) + sum_j gD_j(m) M_j(k)) + kappa_p sum_j gDp_{j,p}(m) M_j(k).
 // The inverse transform is a forward transform of conj(G X) re-laid out through
 // LDS: g_y = 2 conj(DFT(conj(G X))).
+#include <type_traits>
+
 #include "fft_pass.h"
 #include "tacaw_internal.h"
 
@@ -38,7 +47,12 @@ struct BwdShape<1024> {
   static constexpr int N1 = 16, W = 8;
 };
 
-template <int L, typename InT>
+// DW: the window-parameter derivative is wanted (dwin_t set). It needs the
+// centred samples again after both transforms; they are re-read then rather
+// than kept in registers through the transforms.
+// MT: mean term. 0: none (no mean subtracted); 1: accumulate its sum for the
+// separate pass; 2: from the forward pass's bin sums, subtracted at the stores.
+template <int L, typename InT, bool DW, int MT>
 __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
     bwd_kernel(const BwdArgs a) {
   constexpr int N1 = BwdShape<L>::N1;
@@ -54,11 +68,13 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
   __shared__ float s_win[L];
   __shared__ float s_dwin[L];
   __shared__ double red[2 * NT];
+  __shared__ float s_G[L * W];        // upstream weight G(bin, pixel) of the current probe
+  __shared__ float s_mk[kMaxDet * W]; // detector masks of the tile's pixels
 
   const int tid = threadIdx.x;
   const int px = tid % W;
   const int n2 = tid / W;
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile();
   const int n_k = a.n_k;
   const int64_t k = (int64_t)tile * W + px;
   const bool kvalid = k < n_k;
@@ -66,14 +82,14 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
   for (int i = tid; i < L; i += NT) {
     s_tw[i] = a.tw[i];
     s_win[i] = a.win_t[i];
-    s_dwin[i] = a.dwin_t ? a.dwin_t[i] : 0.0f;
+    if constexpr (DW) s_dwin[i] = a.dwin_t[i];
+  }
+  for (int e = tid; e < kMaxDet * W; e += NT) {
+    const int d = e / W;
+    const int64_t kk = (int64_t)tile * W + e % W;
+    s_mk[e] = (d < a.n_det && kk < n_k) ? (float)a.masks[(int64_t)d * n_k + kk] : 0.0f;
   }
   __syncthreads();
-
-  // masks of this pixel
-  float mk[kMaxDet];
-#pragma unroll
-  for (int d = 0; d < kMaxDet; ++d) mk[d] = (d < a.n_det) ? (float)a.masks[(int64_t)d * n_k + kc] : 0.0f;
 
   const int H = a.hop;
   const bool half_hop = (2 * H == L);
@@ -81,28 +97,59 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
 
   for (int i = 0; i < a.n_probes; ++i) {
     const int p = a.probe0 + i;
-    // upstream weight for the thread's bins
-    // (bins outside the energy window have no output row and weight 0)
-    float Gt[N1];
-#pragma unroll
-    for (int t = 0; t < N1; ++t) {
-      int r = F::bin(t, n2) + a.roi_half;  // output row of the bin
-      if (r >= L) r -= L;
-      const int n_om = a.n_om;
-      double g = 0.0;
-      if (r < n_om) {
-        if (a.gS) g += a.kappa_S * a.gS[(int64_t)r * n_k + kc];
-        for (int d = 0; d < a.n_det; ++d) {
-          double c = 0.0;
-          if (a.gD) c += a.kappa_S * a.gD[(int64_t)d * n_om + r];
-          if (a.gDp) c += a.kappa_p * a.gDp[((int64_t)d * a.n_probe_total + p) * n_om + r];
-          g += c * (double)mk[d];
+    // upstream weight of every (bin, pixel) of the tile; it depends on the probe
+    // only through the per-probe detector term. Bins outside the energy window
+    // have no output row and weight 0. (The previous probe's reads of s_G ended
+    // before the barriers at the end of its loop.)
+    if (i == 0 || a.gDp) {
+      for (int e = tid; e < L * W; e += NT) {
+        const int x = e % W;
+        int r = e / W + a.roi_half;  // output row of bin e / W
+        if (r >= L) r -= L;
+        const int n_om = a.n_om;
+        const int64_t kk = (int64_t)tile * W + x;
+        double g = 0.0;
+        if (r < n_om) {
+          if (a.gS) g += a.kappa_S * a.gS[(int64_t)r * n_k + (kk < n_k ? kk : n_k - 1)];
+          for (int d = 0; d < a.n_det; ++d) {
+            double c = 0.0;
+            if (a.gD) c += a.kappa_S * a.gD[(int64_t)d * n_om + r];
+            if (a.gDp) c += a.kappa_p * a.gDp[((int64_t)d * a.n_probe_total + p) * n_om + r];
+            g += c * (double)s_mk[d * W + x];
+          }
+          if (a.qfac) g *= a.qfac[r];
         }
-        if (a.qfac) g *= a.qfac[r];
+        s_G[e] = (float)g;
       }
-      Gt[t] = (float)g;
+      __syncthreads();
     }
-    const double2 mu = a.mu ? a.mu[(int64_t)p * n_k + kc] : make_double2(0.0, 0.0);
+    // mu = c + delta, delta = (sum over the used frames of psi - c) / N_used
+    double2 mu = make_double2(0.0, 0.0), delta = make_double2(0.0, 0.0);
+    if constexpr (MT != 0) {
+      const double2 cr = a.cref[(int64_t)p * n_k + kc];
+      const double2 ms = a.msum[(int64_t)p * n_k + kc];
+      delta = make_double2(ms.x * a.inv_nused, ms.y * a.inv_nused);
+      mu = make_double2(cr.x + delta.x, cr.y + delta.y);
+    }
+    // MT 2: the mean term of this probe and pixel, divided by N_used
+    float2 fix = make_float2(0.f, 0.f);
+    double2 fixd = make_double2(0.0, 0.0);
+    if constexpr (MT == 2) {
+      double2 gm = make_double2(0.0, 0.0);
+      for (int b = 0; b < a.n_corr; ++b) {
+        const int m = b == 0 ? 0 : (b == 1 ? 1 : L - 1);
+        const double g = 2.0 * (double)s_G[m * W + px];
+        const double2 wb = a.wbin[b];
+        const double2 x = a.xs[((int64_t)p * kMaxCorr + b) * n_k + kc];
+        // sum_s X_s(m) = sum_s X'_s(m) - N_s delta W(m)
+        const double sx = x.x - a.n_seg * (delta.x * wb.x - delta.y * wb.y);
+        const double sy = x.y - a.n_seg * (delta.x * wb.y + delta.y * wb.x);
+        gm.x += g * (wb.x * sx + wb.y * sy);  // g conj(W) (sx + i sy)
+        gm.y += g * (wb.x * sy - wb.y * sx);
+      }
+      fixd = make_double2(gm.x * a.inv_nused, gm.y * a.inv_nused);
+      fix = make_float2((float)fixd.x, (float)fixd.y);
+    }
     const int64_t kin = pix_off(kc, a.nx, a.row_stride);
     const InT* inp = (const InT*)a.in + (int64_t)i * a.pstride + kin;
     InT* gp = (InT*)a.grad + (int64_t)i * a.pstride + kin;
@@ -113,30 +160,34 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
 
     for (int s = 0; s < a.n_seg; ++s) {
       const int64_t seg0 = (int64_t)s * H;
-      float2 z[N1], v[N1], X[N1];
+      auto centred = [&](int n1) -> float2 {
+        const InT x = inp[(seg0 + N2 * n1 + n2) * a.fstride];
+        return make_float2((float)((double)x.x - mu.x), (float)((double)x.y - mu.y));
+      };
+      float2 v[N1];
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) {
-        const InT x = inp[(seg0 + N2 * n1 + n2) * a.fstride];
-        z[n1] = make_float2((float)((double)x.x - mu.x), (float)((double)x.y - mu.y));
+        const float2 z = centred(n1);
         const float w = s_win[n2 * N1 + n1];
-        v[n1] = make_float2(w * z[n1].x, w * z[n1].y);
+        v[n1] = make_float2(w * z.x, w * z.y);
       }
-      F::run(v, X, xbuf, s_tw, px, n2);
+      F::run(v, v, xbuf, s_tw, px, n2);
       // weight by G, accumulate the loss value, write conj(G X) in natural order
 #pragma unroll
       for (int t = 0; t < N1; ++t) {
-        const float pw = X[t].x * X[t].x + X[t].y * X[t].y;
-        dLval += (double)Gt[t] * (double)pw;
-        xbuf[F::bin(t, n2) * W + px] = make_float2(Gt[t] * X[t].x, -Gt[t] * X[t].y);
+        const float gt = s_G[F::bin(t, n2) * W + px];
+        const float pw = v[t].x * v[t].x + v[t].y * v[t].y;
+        dLval += (double)gt * (double)pw;
+        xbuf[F::bin(t, n2) * W + px] = make_float2(gt * v[t].x, -gt * v[t].y);
       }
       __syncthreads();
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) v[n1] = xbuf[(N2 * n1 + n2) * W + px];
       __syncthreads();
-      F::run(v, X, xbuf, s_tw, px, n2);
+      F::run(v, v, xbuf, s_tw, px, n2);
       // g_y = 2 conj(X), back to the time layout t = N2 n1 + n2
 #pragma unroll
-      for (int t = 0; t < N1; ++t) xbuf[F::bin(t, n2) * W + px] = make_float2(2.f * X[t].x, -2.f * X[t].y);
+      for (int t = 0; t < N1; ++t) xbuf[F::bin(t, n2) * W + px] = make_float2(2.f * v[t].x, -2.f * v[t].y);
       __syncthreads();
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) v[n1] = xbuf[(N2 * n1 + n2) * W + px];
@@ -145,12 +196,17 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) {
         const float w = s_win[n2 * N1 + n1];
-        const float dw = s_dwin[n2 * N1 + n1];
         const float2 gy = v[n1];
-        dA += (double)dw * ((double)gy.x * z[n1].x + (double)gy.y * z[n1].y);
+        if constexpr (DW) {
+          const float2 z = centred(n1);
+          const float dw = s_dwin[n2 * N1 + n1];
+          dA += (double)dw * ((double)gy.x * z.x + (double)gy.y * z.y);
+        }
         v[n1] = make_float2(w * gy.x, w * gy.y);
-        gsum.x += (double)v[n1].x;
-        gsum.y += (double)v[n1].y;
+        if constexpr (MT == 1) {
+          gsum.x += (double)v[n1].x;
+          gsum.y += (double)v[n1].y;
+        }
       }
       const bool last = (s == a.n_seg - 1);
 #pragma unroll
@@ -168,24 +224,33 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
         }
         if (store && kvalid) {
           InT outv;
-          outv.x = o.x;
-          outv.y = o.y;
+          if constexpr (MT == 2 && sizeof(outv.x) == 8) {
+            outv.x = (double)o.x - fixd.x;
+            outv.y = (double)o.y - fixd.y;
+          } else if constexpr (MT == 2) {
+            outv.x = o.x - fix.x;
+            outv.y = o.y - fix.y;
+          } else {
+            outv.x = o.x;
+            outv.y = o.y;
+          }
           gp[(seg0 + N2 * n1 + n2) * a.fstride] = outv;
         }
       }
     }
-    // mean-term sum of this probe and pixel
-    double2* rr = reinterpret_cast<double2*>(xbuf);
-    rr[tid] = gsum;
-    __syncthreads();
-    if (n2 == 0 && kvalid) {
-      double2 t = make_double2(0.0, 0.0);
+    if constexpr (MT == 1) {  // mean-term sum of this probe and pixel
+      double2* rr = reinterpret_cast<double2*>(xbuf);
+      rr[tid] = gsum;
+      __syncthreads();
+      if (n2 == 0 && kvalid) {
+        double2 t = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int r = 0; r < N2; ++r) {
-        t.x += rr[r * W + px].x;
-        t.y += rr[r * W + px].y;
+        for (int r = 0; r < N2; ++r) {
+          t.x += rr[r * W + px].x;
+          t.y += rr[r * W + px].y;
+        }
+        a.gmean[(int64_t)i * n_k + k] = t;
       }
-      a.gmean[(int64_t)i * n_k + k] = t;
     }
     __syncthreads();
   }
@@ -247,10 +312,28 @@ __global__ void bwd_wparam_kernel(const double* part, int n, double c, double* o
 template <int L>
 static hipError_t launch_bl(int in_dtype, const BwdArgs& a, int n_tiles, hipStream_t st) {
   constexpr int NT = BwdShape<L>::W * (L / BwdShape<L>::N1);
-  if (in_dtype == 1)
-    hipLaunchKernelGGL((bwd_kernel<L, double2>), dim3(n_tiles), dim3(NT), 0, st, a);
-  else
-    hipLaunchKernelGGL((bwd_kernel<L, float2>), dim3(n_tiles), dim3(NT), 0, st, a);
+  const bool dw = a.dwin_t != nullptr;
+  const int mt = a.mean_global ? (a.n_corr > 0 ? 2 : 1) : 0;
+  auto go = [&](auto in_t, auto dw_c, auto mt_c) {
+    hipLaunchKernelGGL((bwd_kernel<L, decltype(in_t), decltype(dw_c)::value, decltype(mt_c)::value>),
+                       dim3(n_tiles), dim3(NT), 0, st, a);
+  };
+  using T0 = std::false_type;
+  using T1 = std::true_type;
+  using M0 = std::integral_constant<int, 0>;
+  using M1 = std::integral_constant<int, 1>;
+  using M2 = std::integral_constant<int, 2>;
+  auto by_mt = [&](auto in_t, auto dw_c) {
+    if (mt == 2) go(in_t, dw_c, M2{});
+    else if (mt == 1) go(in_t, dw_c, M1{});
+    else go(in_t, dw_c, M0{});
+  };
+  auto by_dw = [&](auto in_t) {
+    if (dw) by_mt(in_t, T1{});
+    else by_mt(in_t, T0{});
+  };
+  if (in_dtype == 1) by_dw(double2{});
+  else by_dw(float2{});
   return hipGetLastError();
 }
 

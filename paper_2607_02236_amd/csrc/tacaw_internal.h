@@ -119,6 +119,15 @@ hipError_t launch_detector(const double* S, const double* masks, int32_t n_det, 
                            int32_t n_k, double* D, hipStream_t st);
 
 // Adjoint (tacaw_adjoint.hip).
+// Tile of this workgroup. Workgroups are dealt to the 8 XCDs round-robin
+// (workgroup b runs on XCD b mod 8); this gives each XCD a contiguous range of
+// tiles, so neighbouring tiles (adjacent pixels of the same frame rows) go
+// through the same L2. A bijection of [0, gridDim.x).
+__device__ __forceinline__ int xcd_tile() {
+  const int b = blockIdx.x, n = gridDim.x, q = n / 8, r = n % 8, x = b % 8;
+  return x * q + (x < r ? x : r) + b / 8;
+}
+
 struct BwdArgs {
   const void* in;
   int64_t pstride, fstride;
@@ -133,8 +142,11 @@ struct BwdArgs {
   const float* win_t;      // [N2][N1]
   const float* dwin_t;     // [N2][N1] d w / d r (HANN_WIDTH) or null
   const float2* tw;        // [N2][N1]
-  const double2* cref;     // reference (first frame or exact mean)
-  const double2* mu;       // [n_probe][n_k] exact mean (GLOBAL) for the adjoint
+  const double2* cref;     // [n_probe][n_k] reference c (first frame or exact mean)
+  const double2* msum;     // [n_probe][n_k] FP64 sum over the used frames of psi - c
+  const double2* xs;       // [n_probe][kMaxCorr][n_k] FP64 sum over chunks of X' at bins 0, 1, L-1
+  int32_t n_corr;          // bins where the window's DFT is nonzero (1 or 3), 0 = any bin
+  double2 wbin[kMaxCorr];  // the window's DFT at bins 0, 1, L-1
   const double* gS;        // [n_om][n_k] or null
   const double* gD;        // [n_det][n_om] or null
   const double* gDp;       // [n_det][n_probe][n_om] or null

@@ -189,7 +189,6 @@ struct tacaw_plan_s {
   int64_t dpart_bytes = 0;
   void* ring = nullptr;
   void* fmat = nullptr;     // DFT-GEMM operand (GEMM transforms)
-  double2* mu = nullptr;    // exact means for the adjoint
   double* scratch = nullptr;
   int64_t scratch_bytes = 0;
   float* gscale = nullptr;  // GEMM form: [P][n_k]
@@ -949,10 +948,11 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   seg_fft_split(P->L, &n1b, &n2b);
   if (n1b != P->N1) return fail(TACAW_ERR_UNSUPPORTED, "table split mismatch");
   const bool global = P->d.mean_mode == TACAW_MEAN_GLOBAL;
+  // the mean term comes from the forward pass's bin sums when the window's DFT
+  // lives on bins 0, +-1 (those sums exist); otherwise a second pass applies it
+  const int n_corr = (global && P->strategy == kRefFirstFrame) ? P->n_corr : 0;
   const int Wb = bwd_tile_pixels(P->L);
   const int n_tiles = (P->n_k + Wb - 1) / Wb;
-  if (global && !P->mu)
-    TRY(P->alloc((void**)&P->mu, (int64_t)P->d.n_probe * P->n_k * 16, "adjoint means"));
   const int64_t need = (int64_t)n_probes * P->n_k * 16 + (int64_t)n_tiles * 16;
   if (need > P->scratch_bytes) {
     P->release((void**)&P->scratch);
@@ -960,10 +960,6 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
     TRY(P->alloc((void**)&P->scratch, need, "adjoint scratch"));
     P->scratch_bytes = need;
   }
-  if (global)
-    TRY(hip_check(launch_mean_exact(frames, P->d.in_dtype, pstride, fstride, P->d.nx, P->rs,
-                                    P->n_used, probe0, n_probes, P->n_k, P->mu, P->st),
-                  "adjoint mean"));
   BwdArgs b{};
   b.in = frames;
   b.pstride = pstride;
@@ -987,7 +983,10 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   b.dwin_t = P->d.window == TACAW_WIN_HANN_WIDTH ? P->dwin_t : nullptr;
   b.tw = P->tw;
   b.cref = P->cref;
-  b.mu = global ? P->mu : nullptr;
+  b.msum = P->msum;
+  b.xs = P->xs;
+  b.n_corr = n_corr;
+  for (int i = 0; i < kMaxCorr; ++i) b.wbin[i] = P->wbin[i];
   b.gS = gS;
   b.gD = gD;
   b.gDp = gDp;
@@ -998,7 +997,8 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   b.gmean = (double2*)P->scratch;
   b.dwpart = P->scratch + (int64_t)n_probes * P->n_k * 2;
   TRY(hip_check(launch_bwd(P->L, P->d.in_dtype, b, n_tiles, P->st), "adjoint kernel"));
-  if (global) TRY(hip_check(launch_bwd_mean_fix(b, P->d.in_dtype, P->st), "adjoint mean term"));
+  if (global && n_corr == 0)
+    TRY(hip_check(launch_bwd_mean_fix(b, P->d.in_dtype, P->st), "adjoint mean term"));
   if (grad_wparam && P->d.window == TACAW_WIN_HANN_WIDTH) {
     const std::vector<double> w = make_window(P->d.window, P->L, P->d.window_param);
     const std::vector<double> dw = make_window_dr(P->L, P->d.window_param);

@@ -273,8 +273,10 @@ class Plan:
         if frames.shape[1] < self.info()["frames_used"]:
             raise ValueError("backward needs every frame that enters a chunk (frames_used)")
         if grad is None:
+            # the adjoint writes every frame that enters a chunk; only the rest is zeroed
             grad = torch.empty_strided(frames.shape, frames.stride(), dtype=frames.dtype,
-                                       device=frames.device).zero_()
+                                       device=frames.device)
+            grad[:, self.info()["frames_used"]:].zero_()
         if grad.stride() != frames.stride():
             raise ValueError("grad must have the strides of frames")
         if grad_wparam is None:
