@@ -225,4 +225,40 @@ __host__ __device__ __forceinline__ void dft_inplace(float2 (&a)[N]) {
   }
 }
 
+// Pass 2 for N2 > N1: the N2-point DFT of one k1 is shared by G = N2 / N1
+// threads. Thread g computes the outputs k2 = G r + g (r < N1) from
+//   y[n] = W_{N2}^{n g} sum_{j < G} A[n + N1 j] W_G^{j g},  X = DFT_{N1}(y),
+// i.e. one decimation-in-frequency stage folded into the loads, so no second
+// exchange is needed. G and g are compile-time here (g is uniform per wave).
+// c(n) = A[n] (an accessor: registers or LDS). dif_fold_part computes the
+// folded sums y[n] for N0 <= n < NE without the final twiddles.
+template <int N1, int G, int g, int N0, int NE, typename Col>
+__device__ __forceinline__ void dif_fold_part(const Col& c, float2 (&y)[N1]) {
+#pragma unroll
+  for (int n = N0; n < NE; ++n) {
+    float2 s = c(n);
+#pragma unroll
+    for (int j = 1; j < G; ++j) {
+      const float2 x = c(n + N1 * j);
+      // rotate by W_G^{j g} = exp(-2 pi i j g / G)
+      const int e = (j * g) % G;
+      float2 t;
+      if (G == 2) {
+        t = e == 0 ? x : make_float2(-x.x, -x.y);
+      } else {  // G == 4
+        t = e == 0 ? x : e == 1 ? make_float2(x.y, -x.x) : e == 2 ? make_float2(-x.x, -x.y)
+                                                           : make_float2(-x.y, x.x);
+      }
+      s.x += t.x;
+      s.y += t.y;
+    }
+    y[n] = s;
+  }
+}
+template <int N1, int G, int g, typename Col>
+__device__ __forceinline__ void dif_combine(const Col& c, float2 (&y)[N1]) {
+  dif_fold_part<N1, G, g, 0, N1>(c, y);
+  if constexpr (g != 0) TwiddleRow<N1, N1 * G, g>::apply(y);
+}
+
 }  // namespace tacaw

@@ -26,37 +26,11 @@
 
 #include <type_traits>
 
+#include "buffer_io.h"
 #include "regfft.h"
 #include "tacaw_internal.h"
 
 namespace tacaw {
-
-// Raw buffer load of one element at base + off (off < range, else 0): the base
-// and the range live in scalar registers, the offset in one VGPR.
-template <typename T>
-__device__ __forceinline__ T buffer_load(const char* base, uint32_t range, uint32_t off) {
-  __amdgpu_buffer_rsrc_t r =
-      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)range, 0x00020000);
-  if constexpr (sizeof(T) == 8) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
-  } else {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
-  }
-}
-
-// The same with a scalar offset: element at base + soffset + off, range counted
-// from base (one descriptor serves several row groups).
-template <typename T>
-__device__ __forceinline__ T buffer_load_so(const char* base, uint32_t range, uint32_t off,
-                                            uint32_t soff) {
-  __amdgpu_buffer_rsrc_t r =
-      __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)range, 0x00020000);
-  if constexpr (sizeof(T) == 8) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, (int)soff, 0));
-  } else {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, (int)soff, 0));
-  }
-}
 
 template <int L>
 struct FftShape;
@@ -94,40 +68,6 @@ struct FftShape<200> {
   static constexpr int N1 = 10, W = 32;
 };
 
-// Pass 2 for N2 > N1: the N2-point DFT of one k1 is shared by G = N2 / N1
-// threads. Thread g computes the outputs k2 = G r + g (r < N1) from
-//   y[n] = W_{N2}^{n g} sum_{j < G} A[n + N1 j] W_G^{j g},  X = DFT_{N1}(y),
-// i.e. one decimation-in-frequency stage folded into the loads, so no second
-// exchange is needed. G and g are compile-time here (g is uniform per wave).
-template <int N1, int G, int g>
-__device__ __forceinline__ void dif_combine(const float2* __restrict__ col, int stride,
-                                            float2 (&y)[N1]) {
-  constexpr int N2 = N1 * G;
-#pragma unroll
-  for (int n = 0; n < N1; ++n) {
-    float2 s = col[n * stride];
-#pragma unroll
-    for (int j = 1; j < G; ++j) {
-      const float2 x = col[(n + N1 * j) * stride];
-      // rotate by W_G^{j g} = exp(-2 pi i j g / G)
-      const int e = (j * g) % G;
-      float2 t;
-      if (G == 2) {
-        t = e == 0 ? x : make_float2(-x.x, -x.y);
-      } else {  // G == 4
-        t = e == 0 ? x : e == 1 ? make_float2(x.y, -x.x) : e == 2 ? make_float2(-x.x, -x.y)
-                                                           : make_float2(-x.y, x.x);
-      }
-      s.x += t.x;
-      s.y += t.y;
-    }
-    y[n] = s;
-  }
-  if constexpr (g != 0) {
-    TwiddleRow<N1, N2, g>::apply(y);
-  }
-}
-
 // LEAN: every chunk of the launch lies inside the push buffer and H = L/2, so
 // all loads use uniform row bases and the frames to count in the mean sum are
 // known per n1 at compile time. The general variant also reads the ring, takes
@@ -137,8 +77,15 @@ __device__ __forceinline__ void dif_combine(const float2* __restrict__ col, int 
 // variant reading every frame from the ring (deferred streaming); MODE 3: MODE 1
 // when a whole chunk of frames spans less than 2 GiB, so one buffer descriptor per
 // chunk serves all row groups through a scalar offset (fewer scalar registers).
+#ifndef TACAW_XBUF_TILES
+#define TACAW_XBUF_TILES 2  // exchange tiles: 2 = alternate per chunk (one barrier), 1 = two barriers
+#endif
+#ifndef TACAW_WAVES_PER_EU
+#define TACAW_WAVES_PER_EU 1  // minimum waves per SIMD the register allocation must allow
+#endif
 template <int L, typename InT, bool SUB64, bool DP, int MODE>
 __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
+    __attribute__((amdgpu_waves_per_eu(TACAW_WAVES_PER_EU)))
     seg_fft_kernel(const SegArgs a) {
   constexpr bool LEAN = MODE != 0;
   constexpr bool RING = MODE == 2;
@@ -159,7 +106,8 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
 
   // two exchange tiles [k1][n2][px] used by alternate chunks, so one barrier per
   // chunk suffices; tile 0 is reused for the per-probe reductions
-  __shared__ float2 xbuf2[2 * N1 * KROW];
+  constexpr int NBUF = TACAW_XBUF_TILES;
+  __shared__ float2 xbuf2[NBUF * N1 * KROW];
   float2* const xbuf = xbuf2;
   __shared__ float2 s_tw[L];          // [n2][k1]
   __shared__ float s_win[L];          // [n2][n1]
@@ -401,8 +349,9 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
       // tile (cc & 1), cc counting this thread block's chunks: the reads of
       // chunk cc - 2 from it finished before the barrier of chunk cc - 1, so only
       // the barrier after the writes is needed
-      float2* const xb = xbuf2 + (cc & 1) * (N1 * KROW);
+      float2* const xb = xbuf2 + (NBUF == 2 ? (cc & 1) : 0) * (N1 * KROW);
       ++cc;
+      if constexpr (NBUF == 1) __syncthreads();  // the previous chunk's reads are done
 #pragma unroll
       for (int k1 = 0; k1 < N1; ++k1) xb[k1 * KROW + n2 * W + px] = v[k1];
       __syncthreads();
@@ -415,6 +364,9 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
           const float2* col = xb + (j + N2 * q) * KROW + px;
 #pragma unroll
           for (int r = 0; r < N2; ++r) X[r] = col[r * W];
+          // all reads issued before the first use (the general variant has no
+          // registers to spare for that)
+          if constexpr (LEAN) __builtin_amdgcn_sched_barrier(0);
           dft_inplace<N2>(X);
 #pragma unroll
           for (int k2 = 0; k2 < N2; ++k2) {
@@ -436,14 +388,49 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
         // G-mode: G threads share the N2-point DFT of k1 = j % N1
         const float2* col = xb + k1g * KROW + px;
         float2 X[N1];
-        if constexpr (G == 2) {
-          if (gg == 0) dif_combine<N1, 2, 0>(col, W, X);
-          else dif_combine<N1, 2, 1>(col, W, X);
+        if constexpr (G == 2 && LEAN) {
+          // all 32 reads first, so that their latencies overlap
+          float2 c[N2];
+#pragma unroll
+          for (int n = 0; n < N2; ++n) c[n] = col[n * W];
+          __builtin_amdgcn_sched_barrier(0);
+          auto cr = [&](int n) { return c[n]; };
+          if (gg == 0) dif_combine<N1, 2, 0>(cr, X);
+          else dif_combine<N1, 2, 1>(cr, X);
+        } else if constexpr (G == 2) {
+          // the general variant has no registers to spare: read as used
+          auto cl = [&](int n) { return col[n * W]; };
+          if (gg == 0) dif_combine<N1, 2, 0>(cl, X);
+          else dif_combine<N1, 2, 1>(cl, X);
+        } else if constexpr (!LEAN) {
+          auto cl = [&](int n) { return col[n * W]; };
+          if (gg == 0) dif_combine<N1, 4, 0>(cl, X);
+          else if (gg == 1) dif_combine<N1, 4, 1>(cl, X);
+          else if (gg == 2) dif_combine<N1, 4, 2>(cl, X);
+          else dif_combine<N1, 4, 3>(cl, X);
         } else {
-          if (gg == 0) dif_combine<N1, 4, 0>(col, W, X);
-          else if (gg == 1) dif_combine<N1, 4, 1>(col, W, X);
-          else if (gg == 2) dif_combine<N1, 4, 2>(col, W, X);
-          else dif_combine<N1, 4, 3>(col, W, X);
+          // G = 4: the 64 values are read and folded in two halves of 32 (all 64
+          // at once would exceed the register budget)
+          constexpr int HN = N1 / 2;
+          auto fold_half = [&](auto h) {
+            constexpr int H0 = decltype(h)::value * HN;
+            float2 c[4 * HN];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+              for (int n = 0; n < HN; ++n) c[q * HN + n] = col[(H0 + n + N1 * q) * W];
+            __builtin_amdgcn_sched_barrier(0);
+            auto cr = [&](int m) { return c[(m / N1) * HN + m % N1 - H0]; };
+            if (gg == 0) dif_fold_part<N1, 4, 0, H0, H0 + HN>(cr, X);
+            else if (gg == 1) dif_fold_part<N1, 4, 1, H0, H0 + HN>(cr, X);
+            else if (gg == 2) dif_fold_part<N1, 4, 2, H0, H0 + HN>(cr, X);
+            else dif_fold_part<N1, 4, 3, H0, H0 + HN>(cr, X);
+          };
+          fold_half(std::integral_constant<int, 0>{});
+          fold_half(std::integral_constant<int, 1>{});
+          if (gg == 1) TwiddleRow<N1, N2, 1>::apply(X);
+          else if (gg == 2) TwiddleRow<N1, N2, 2>::apply(X);
+          else if (gg == 3) TwiddleRow<N1, N2, 3>::apply(X);
         }
         dft_inplace<N1>(X);
 #pragma unroll

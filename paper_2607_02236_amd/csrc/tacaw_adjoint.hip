@@ -6,6 +6,8 @@
 //   g_z(t)  = w(t) g_y(t)
 //   grad psi(n) = sum over the chunks holding n of g_z(n - sH)
 //                 - [n < N_used] (1 / N_used) sum_s sum_t g_z_s(t)   (GLOBAL mean)
+//   dLval/dr = sum Re[conj(g_y) z] dw/dr - 2 Lval sum_t w dw/dr / sum_t w^2
+// with G_p(m,k) = kappa_S (gS(m,k) + sum_j gD_j(m) M_j(k)) + kappa_p sum_j gDp_{j,p}(m) M_j(k).
 // The mean-term sum is sum_s sum_m 2 G(m) X_s(m) conj(W(m)), W the window's DFT.
 // For a window whose W vanishes outside bins {0, 1, L-1} it needs only the FP64
 // chunk sums of X at those bins, which the forward pass kept for its exact mean
@@ -13,13 +15,23 @@
 // then subtracted as each frame is stored. Otherwise the sum is accumulated here
 // and a second pass subtracts it. mu = c + (FP64 sum of psi - c) / N_used, also
 // from the forward pass.
-//   dLval/dr = sum Re[conj(g_y) z] dw/dr - 2 Lval sum_t w dw/dr / sum_t w^2
-// with G_p(m,k) = kappa_S (gS(m,k) + sum_j gD_j(m) M_j(k)) + kappa_p sum_j gDp_{j,p}(m) M_j(k).
-// The inverse transform is a forward transform of conj(G X) re-laid out through
-// LDS: g_y = 2 conj(DFT(conj(G X))).
+//
+// Transforms (L = N1 N2, t = N2 n1 + n2, m = k1 + N1 k2): the forward one is the
+// chunk kernel's (N1-point DFTs over n1 in registers, inter-pass twiddle, one LDS
+// exchange, N2-point DFTs over n2, as G = N2 / N1 threads with a folded
+// decimation-in-frequency stage when N2 > N1). The inverse runs the same steps
+// in reverse order on conj(G X):
+//   conj(U(k1, n2)) = sum_k2 conj(Z(k1 + N1 k2)) exp(-2 pi i k2 n2 / N2)   (Z = G X)
+//   conj(g_y(t)) / 2 = sum_k1 conj(U(k1, n2)) exp(-2 pi i k1 n2 / L) exp(-2 pi i k1 n1 / N1)
+// The first line is computed by the threads that hold the bins (with G threads
+// per k1: thread g forms C_g(n) = exp(-2 pi i g n / N2) DFT_N1(conj Z_g)(n), and
+// conj(U(k1, n + N1 j)) = sum_g exp(-2 pi i g j / G) C_g(n)); one LDS exchange
+// brings the columns back to the time layout for the second line. Two exchanges
+// and two barriers per chunk.
 #include <type_traits>
 
-#include "fft_pass.h"
+#include "buffer_io.h"
+#include "regfft.h"
 #include "tacaw_internal.h"
 
 namespace tacaw {
@@ -47,6 +59,15 @@ struct BwdShape<1024> {
   static constexpr int N1 = 16, W = 8;
 };
 
+// x exp(-2 pi i e / G), G in {2, 4}
+template <int G>
+__device__ __forceinline__ float2 rot_g(float2 x, int e) {
+  e %= G;
+  if (e == 0) return x;
+  if (G == 2 || e == 2) return make_float2(-x.x, -x.y);
+  return e == 1 ? make_float2(x.y, -x.x) : make_float2(-x.y, x.x);
+}
+
 // DW: the window-parameter derivative is wanted (dwin_t set). It needs the
 // centred samples again after both transforms; they are re-read then rather
 // than kept in registers through the transforms.
@@ -57,23 +78,30 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
     bwd_kernel(const BwdArgs a) {
   constexpr int N1 = BwdShape<L>::N1;
   constexpr int W = BwdShape<L>::W;
-  using F = Fft2<L, N1, W>;
-  constexpr int N2 = F::N2;
+  constexpr int N2 = L / N1;
   constexpr int NT = W * N2;
   constexpr int HALF = N1 / 2;
-  static_assert(F::LDS >= L * W, "exchange tile must hold a natural-order [L][W] tile");
+  constexpr int R = N2 <= N1 ? N1 / N2 : 1;  // pass-2 DFTs per thread (N2 <= N1)
+  constexpr int G = N2 > N1 ? N2 / N1 : 1;   // threads per pass-2 DFT (N2 > N1)
+  constexpr int KROW = N2 * W + W;           // float2 per k1 row of an exchange tile
+  constexpr int TILE = N1 * KROW;
+  static_assert(G == 1 || G == 2 || G == 4, "pass-2 split");
 
-  __shared__ float2 xbuf[F::LDS];
-  __shared__ float2 s_tw[L];
-  __shared__ float s_win[L];
-  __shared__ float s_dwin[L];
+  __shared__ float2 xbuf2[2 * TILE];  // forward exchange tile, inverse exchange tile
+  __shared__ float2 s_tw[L];          // [n2][k1] exp(-2 pi i n2 k1 / L)
+  __shared__ float s_win[L];          // [n2][n1]
+  __shared__ float s_dwin[DW ? L : 1];
   __shared__ double red[2 * NT];
-  __shared__ float s_G[L * W];        // upstream weight G(bin, pixel) of the current probe
-  __shared__ float s_mk[kMaxDet * W]; // detector masks of the tile's pixels
+  __shared__ float s_mk[kMaxDet * W];  // detector masks of the tile's pixels
+  float2* const xa = xbuf2;
+  float2* const xi = xbuf2 + TILE;
 
   const int tid = threadIdx.x;
   const int px = tid % W;
-  const int n2 = tid / W;
+  const int n2 = tid / W;  // time role: residue n2; bin role: j = n2
+  const int j = n2;
+  const int k1g = j % N1;
+  const int gg = j / N1;   // uniform per wave
   const int tile = xcd_tile();
   const int n_k = a.n_k;
   const int64_t k = (int64_t)tile * W + px;
@@ -91,37 +119,60 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
   }
   __syncthreads();
 
+  // bin m held as value t by this thread in the bin role
+  auto bin = [&](int t) -> int {
+    if constexpr (G == 1) return (j + N2 * (t / N2)) + N1 * (t % N2);
+    else return k1g + N1 * (G * t + gg);
+  };
+  // upstream weight G_p(m, k) of this pixel; bins outside the energy window
+  // have no output row and weight 0
+  auto weight = [&](int m, int p) -> double {
+    int r = m + a.roi_half;  // output row of bin m
+    if (r >= L) r -= L;
+    const int n_om = a.n_om;
+    double g = 0.0;
+    if (r < n_om) {
+      if (a.gS) g += a.kappa_S * a.gS[(int64_t)r * n_k + kc];
+      for (int d = 0; d < a.n_det; ++d) {
+        double c = 0.0;
+        if (a.gD) c += a.kappa_S * a.gD[(int64_t)d * n_om + r];
+        if (a.gDp) c += a.kappa_p * a.gDp[((int64_t)d * a.n_probe_total + p) * n_om + r];
+        g += c * (double)s_mk[d * W + px];
+      }
+      if (a.qfac) g *= a.qfac[r];
+    }
+    return g;
+  };
+
   const int H = a.hop;
   const bool half_hop = (2 * H == L);
   double dA = 0.0, dLval = 0.0;
+  float Gt[N1];  // weights of the thread's bins (they change per probe only through gDp)
+
+  // frames and gradient: raw buffer accesses, one 32-bit lane offset (n2 rows,
+  // pixel kc) from a uniform row-group base (rows N2 n1 .. N2 n1 + N2 - 1 of a
+  // chunk; the host checks that a group spans less than 2 GiB)
+  constexpr int ESZ = (int)sizeof(InT);
+  const int64_t row_bytes = a.fstride * ESZ;
+  const int64_t kin = pix_off(kc, a.nx, a.row_stride);
+  const uint32_t lane_off = (uint32_t)(((int64_t)n2 * a.fstride + kin) * ESZ);
+  const int64_t span = pix_off((int64_t)n_k - 1, a.nx, a.row_stride) + 1;
+  const uint32_t group_bytes = (uint32_t)((int64_t)(N2 - 1) * row_bytes + span * ESZ);
+  auto group = [&](const void* base, int ii, int ss, int n1) -> char* {
+    int64_t gstride = (int64_t)N2 * row_bytes;  // formed next to each access, not kept
+    asm volatile("" : "+s"(gstride));
+    return (char*)base + (int64_t)ii * a.pstride * ESZ + (int64_t)ss * H * row_bytes + n1 * gstride;
+  };
+  // raw samples of the next chunk, loaded one chunk ahead
+  InT pre[N1];
+#pragma unroll
+  for (int n1 = 0; n1 < N1; ++n1) pre[n1] = buffer_load<InT>(group(a.in, 0, 0, n1), group_bytes, lane_off);
 
   for (int i = 0; i < a.n_probes; ++i) {
     const int p = a.probe0 + i;
-    // upstream weight of every (bin, pixel) of the tile; it depends on the probe
-    // only through the per-probe detector term. Bins outside the energy window
-    // have no output row and weight 0. (The previous probe's reads of s_G ended
-    // before the barriers at the end of its loop.)
     if (i == 0 || a.gDp) {
-      for (int e = tid; e < L * W; e += NT) {
-        const int x = e % W;
-        int r = e / W + a.roi_half;  // output row of bin e / W
-        if (r >= L) r -= L;
-        const int n_om = a.n_om;
-        const int64_t kk = (int64_t)tile * W + x;
-        double g = 0.0;
-        if (r < n_om) {
-          if (a.gS) g += a.kappa_S * a.gS[(int64_t)r * n_k + (kk < n_k ? kk : n_k - 1)];
-          for (int d = 0; d < a.n_det; ++d) {
-            double c = 0.0;
-            if (a.gD) c += a.kappa_S * a.gD[(int64_t)d * n_om + r];
-            if (a.gDp) c += a.kappa_p * a.gDp[((int64_t)d * a.n_probe_total + p) * n_om + r];
-            g += c * (double)s_mk[d * W + x];
-          }
-          if (a.qfac) g *= a.qfac[r];
-        }
-        s_G[e] = (float)g;
-      }
-      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < N1; ++t) Gt[t] = (float)weight(bin(t), p);
     }
     // mu = c + delta, delta = (sum over the used frames of psi - c) / N_used
     double2 mu = make_double2(0.0, 0.0), delta = make_double2(0.0, 0.0);
@@ -138,7 +189,7 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
       double2 gm = make_double2(0.0, 0.0);
       for (int b = 0; b < a.n_corr; ++b) {
         const int m = b == 0 ? 0 : (b == 1 ? 1 : L - 1);
-        const double g = 2.0 * (double)s_G[m * W + px];
+        const double g = 2.0 * (double)(float)weight(m, p);  // the FP32 weight the transform uses
         const double2 wb = a.wbin[b];
         const double2 x = a.xs[((int64_t)p * kMaxCorr + b) * n_k + kc];
         // sum_s X_s(m) = sum_s X'_s(m) - N_s delta W(m)
@@ -150,55 +201,123 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
       fixd = make_double2(gm.x * a.inv_nused, gm.y * a.inv_nused);
       fix = make_float2((float)fixd.x, (float)fixd.y);
     }
-    const int64_t kin = pix_off(kc, a.nx, a.row_stride);
-    const InT* inp = (const InT*)a.in + (int64_t)i * a.pstride + kin;
-    InT* gp = (InT*)a.grad + (int64_t)i * a.pstride + kin;
     float2 carry[HALF];
 #pragma unroll
     for (int u = 0; u < HALF; ++u) carry[u] = make_float2(0.f, 0.f);
     double2 gsum = make_double2(0.0, 0.0);
 
     for (int s = 0; s < a.n_seg; ++s) {
-      const int64_t seg0 = (int64_t)s * H;
-      auto centred = [&](int n1) -> float2 {
-        const InT x = inp[(seg0 + N2 * n1 + n2) * a.fstride];
+      auto centre = [&](const InT& x) -> float2 {
         return make_float2((float)((double)x.x - mu.x), (float)((double)x.y - mu.y));
       };
       float2 v[N1];
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) {
-        const float2 z = centred(n1);
+        const float2 z = centre(pre[n1]);
         const float w = s_win[n2 * N1 + n1];
         v[n1] = make_float2(w * z.x, w * z.y);
       }
-      F::run(v, v, xbuf, s_tw, px, n2);
-      // weight by G, accumulate the loss value, write conj(G X) in natural order
+      // prefetch the next chunk (or the next probe's first chunk)
+      {
+        const bool next_chunk = s + 1 < a.n_seg;
+        if (next_chunk || i + 1 < a.n_probes) {
+          const int ii = next_chunk ? i : i + 1;
+          const int ss = next_chunk ? s + 1 : 0;
+#pragma unroll
+          for (int n1 = 0; n1 < N1; ++n1)
+            pre[n1] = buffer_load<InT>(group(a.in, ii, ss, n1), group_bytes, lane_off);
+        }
+      }
+      // ---- forward transform: time layout -> bin layout X[t] = X(bin(t))
+      dft_inplace<N1>(v);
+#pragma unroll
+      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], s_tw[n2 * N1 + k1]);
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) xa[k1 * KROW + n2 * W + px] = v[k1];
+      __syncthreads();  // (1) forward tile written; the inverse tile's reads of the previous chunk are done
+      float2 X[N1];
+      if constexpr (G == 1) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          float2 Y[N2];
+          const float2* col = xa + (j + N2 * q) * KROW + px;
+#pragma unroll
+          for (int r = 0; r < N2; ++r) Y[r] = col[r * W];
+          dft_inplace<N2>(Y);
+#pragma unroll
+          for (int k2 = 0; k2 < N2; ++k2) X[q * N2 + k2] = Y[k2];
+        }
+      } else {
+        const float2* col = xa + k1g * KROW + px;
+        auto cl = [&](int n) { return col[n * W]; };
+        if constexpr (G == 2) {
+          if (gg == 0) dif_combine<N1, 2, 0>(cl, X);
+          else dif_combine<N1, 2, 1>(cl, X);
+        } else {
+          if (gg == 0) dif_combine<N1, 4, 0>(cl, X);
+          else if (gg == 1) dif_combine<N1, 4, 1>(cl, X);
+          else if (gg == 2) dif_combine<N1, 4, 2>(cl, X);
+          else dif_combine<N1, 4, 3>(cl, X);
+        }
+        dft_inplace<N1>(X);
+      }
+      // ---- weight by G: loss value; conj(Z) = conj(G X)
 #pragma unroll
       for (int t = 0; t < N1; ++t) {
-        const float gt = s_G[F::bin(t, n2) * W + px];
-        const float pw = v[t].x * v[t].x + v[t].y * v[t].y;
-        dLval += (double)gt * (double)pw;
-        xbuf[F::bin(t, n2) * W + px] = make_float2(gt * v[t].x, -gt * v[t].y);
+        const float pw = X[t].x * X[t].x + X[t].y * X[t].y;
+        dLval += (double)Gt[t] * (double)pw;
+        X[t] = make_float2(Gt[t] * X[t].x, -Gt[t] * X[t].y);
       }
-      __syncthreads();
+      // ---- inverse, bin side: conj(U(k1, n2)) (or its G partial sums) into the inverse tile
+      if constexpr (G == 1) {
 #pragma unroll
-      for (int n1 = 0; n1 < N1; ++n1) v[n1] = xbuf[(N2 * n1 + n2) * W + px];
-      __syncthreads();
-      F::run(v, v, xbuf, s_tw, px, n2);
-      // g_y = 2 conj(X), back to the time layout t = N2 n1 + n2
+        for (int q = 0; q < R; ++q) {
+          float2 Y[N2];
 #pragma unroll
-      for (int t = 0; t < N1; ++t) xbuf[F::bin(t, n2) * W + px] = make_float2(2.f * v[t].x, -2.f * v[t].y);
-      __syncthreads();
+          for (int k2 = 0; k2 < N2; ++k2) Y[k2] = X[q * N2 + k2];
+          dft_inplace<N2>(Y);
 #pragma unroll
-      for (int n1 = 0; n1 < N1; ++n1) v[n1] = xbuf[(N2 * n1 + n2) * W + px];
-      __syncthreads();
+          for (int r = 0; r < N2; ++r) xi[(j + N2 * q) * KROW + r * W + px] = Y[r];
+        }
+      } else {
+        dft_inplace<N1>(X);
+        if (gg == 1) TwiddleRow<N1, N2, 1>::apply(X);
+        if constexpr (G == 4) {
+          if (gg == 2) TwiddleRow<N1, N2, 2>::apply(X);
+          else if (gg == 3) TwiddleRow<N1, N2, 3>::apply(X);
+        }
+#pragma unroll
+        for (int n = 0; n < N1; ++n) xi[k1g * KROW + (gg * N1 + n) * W + px] = X[n];
+      }
+      __syncthreads();  // (2) inverse tile written; the forward tile's reads are done
+      // ---- inverse, time side: conj(U(k1, n2)) for every k1, twiddle, N1-point DFT
+      if constexpr (G == 1) {
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) v[k1] = xi[k1 * KROW + n2 * W + px];
+      } else {
+        const int n = n2 % N1, jj = n2 / N1;  // jj is uniform per wave
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) {
+          float2 sum = xi[k1 * KROW + n * W + px];
+#pragma unroll
+          for (int g = 1; g < G; ++g) {
+            const float2 c = rot_g<G>(xi[k1 * KROW + (g * N1 + n) * W + px], g * jj);
+            sum.x += c.x;
+            sum.y += c.y;
+          }
+          v[k1] = sum;
+        }
+      }
+#pragma unroll
+      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], s_tw[n2 * N1 + k1]);
+      dft_inplace<N1>(v);  // v[n1] = conj(g_y(N2 n1 + n2)) / 2
       // g_z = w g_y; r-derivative term; mean-term sum; overlap carry and stores
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) {
         const float w = s_win[n2 * N1 + n1];
-        const float2 gy = v[n1];
-        if constexpr (DW) {
-          const float2 z = centred(n1);
+        const float2 gy = make_float2(2.f * v[n1].x, -2.f * v[n1].y);
+        if constexpr (DW) {  // the chunk's samples again (they were not kept)
+          const float2 z = centre(buffer_load<InT>(group(a.in, i, s, n1), group_bytes, lane_off));
           const float dw = s_dwin[n2 * N1 + n1];
           dA += (double)dw * ((double)gy.x * z.x + (double)gy.y * z.y);
         }
@@ -234,12 +353,13 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
             outv.x = o.x;
             outv.y = o.y;
           }
-          gp[(seg0 + N2 * n1 + n2) * a.fstride] = outv;
+          buffer_store<InT>(outv, group(a.grad, i, s, n1), group_bytes, lane_off);
         }
       }
     }
     if constexpr (MT == 1) {  // mean-term sum of this probe and pixel
-      double2* rr = reinterpret_cast<double2*>(xbuf);
+      __syncthreads();        // the last chunk's reads of the forward tile are done
+      double2* rr = reinterpret_cast<double2*>(xa);
       rr[tid] = gsum;
       __syncthreads();
       if (n2 == 0 && kvalid) {
@@ -251,8 +371,8 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
         }
         a.gmean[(int64_t)i * n_k + k] = t;
       }
+      __syncthreads();  // before the next probe's forward tile writes
     }
-    __syncthreads();
   }
   // workgroup partials of the r-derivative and the loss value
   red[tid] = kvalid ? dA : 0.0;

@@ -939,6 +939,8 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   if (fstride < P->span)
     return fail(TACAW_ERR_INVALID_ARG, "frame_stride must cover a frame ((ny - 1) * row stride + nx)");
   if (n_probes > 1 && pstride < 1) return fail(TACAW_ERR_INVALID_ARG, "probe_stride must be >= 1");
+  if (((int64_t)P->N2 * fstride + P->span) * P->esz > (int64_t)0x7FFFFFFFLL)
+    return fail(TACAW_ERR_UNSUPPORTED, "frame_stride too large for 31-bit row-group offsets");
   if (P->H != P->L && 2 * P->H != P->L)
     return fail(TACAW_ERR_UNSUPPORTED, "backward supports hop = L or hop = L/2");
   if (!is_pow2(P->L)) return fail(TACAW_ERR_UNSUPPORTED, "backward needs a power-of-two seg_len");

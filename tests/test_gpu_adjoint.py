@@ -23,14 +23,19 @@ def ag():
     return autograd
 
 
-@pytest.mark.parametrize("L,H,NT,ny,nx,P,mode,window,r", [
-    (512, 512, 1024, 16, 16, 3, "global", "hann_width", 1.0),   # 2 chunks of 512, no overlap
-    (256, 128, 600, 9, 13, 2, "global", "hann", 1.0),           # 50 % overlap carry, ragged
-    (128, 128, 300, 8, 8, 2, "none", "hann_width", 0.8),
-    (64, 32, 200, 5, 7, 2, "global", "hann_width", 1.1),
+# The mean term of the gradient comes from the forward pass's bin sums when the
+# window's DFT lives on bins {0, +-1} (Hann, width-r Hann at r = 1) or bin 0
+# (rect), and from a separate pass otherwise (r != 1); "none" has no mean term.
+@pytest.mark.parametrize("L,H,NT,ny,nx,P,mode,window,r,dtype", [
+    (512, 512, 1024, 16, 16, 3, "global", "hann_width", 1.0, "c64"),  # 2 chunks of 512, no overlap
+    (256, 128, 600, 9, 13, 2, "global", "hann", 1.0, "c64"),          # 50 % overlap carry, ragged
+    (128, 128, 300, 8, 8, 2, "none", "hann_width", 0.8, "c64"),
+    (64, 32, 200, 5, 7, 2, "global", "hann_width", 1.1, "c64"),       # mean term in a second pass
+    (256, 256, 700, 6, 10, 2, "global", "rect", 1.0, "c64"),          # window DFT on bin 0 only
+    (128, 64, 400, 7, 9, 2, "global", "hann", 1.0, "c128"),
 ])
-def test_adjoint_matches_oracle(ag, L, H, NT, ny, nx, P, mode, window, r):
-    spec = T.SeriesSpec(P, NT, ny, nx, dtype="c64", seed=40 + L, model="lines", n_terms=8)
+def test_adjoint_matches_oracle(ag, L, H, NT, ny, nx, P, mode, window, r, dtype):
+    spec = T.SeriesSpec(P, NT, ny, nx, dtype=dtype, seed=40 + L, model="lines", n_terms=8)
     psi = T.generate(spec)
     masks = T.standard_masks(ny, nx, scale=min(ny, nx) / 128)
     masks[3] = np.random.default_rng(2).random((ny, nx))
