@@ -117,6 +117,9 @@ def main():
     ap.add_argument("--ring-frames", type=int, default=0,
                     help="streaming: deferred ring depth per probe (0: chunks run in the push "
                          "that completes them)")
+    ap.add_argument("--ring-layout", default="tiled", choices=["tiled", "frame"],
+                    help="streaming with --ring-frames: store the ring per pixel tile (default) "
+                         "or per frame")
     ap.add_argument("--resident-frames", type=int, default=512,
                     help="streaming: frames held in HBM per probe; pushes cycle through them "
                          "(4096 = the whole series)")
@@ -197,6 +200,7 @@ def main():
     plan = tacaw.Plan(spec.n_probe, spec.ny, spec.nx, spec.n_frames, L, H, masks=masks,
                       transform=args.form, in_dtype=spec.dtype, time_kernels=True, stream=stream,
                       dt_fs=dt_fs, omega_half=M, ring_frames=args.ring_frames if streaming else 0,
+                      tiled_ring=streaming and args.ring_frames > 0 and args.ring_layout == "tiled",
                       **win)
     R = psi.shape[1]
     pieces = [(f0, min(spec.n_frames, f0 + args.push_frames))
@@ -284,7 +288,8 @@ def main():
                         + f", global mean, {masks.shape[0]} detector masks, transform {args.form}"
                         + (", forward + adjoint (dL/dpsi and dL/dr of sum_j a_j . D_j)" if gradient else "")
                         + (f", pushed in pieces of {args.push_frames} frames" if streaming else "")
-                        + (f", deferred ring of {args.ring_frames} frames" if streaming and args.ring_frames else "")
+                        + (f", deferred ring of {args.ring_frames} frames ({args.ring_layout} layout)"
+                           if streaming and args.ring_frames else "")
                         + (f", energy window |E| <= {args.roi_mev:g} meV ({n_om} bins)" if M else ""),
             "probes": spec.n_probe, "frames": spec.n_frames, "ny": spec.ny, "nx": spec.nx,
             "seg_len": L, "hop": H, "n_omega": n_om, "exit_wave_bytes": b_alg,

@@ -129,6 +129,14 @@ typedef struct {
  * (reading it synchronizes with the plan's stream; -1 if that push completed no
  * chunk). */
 #define TACAW_FLAG_TIME_KERNELS 1
+/* flags: deferred ring mode (ring_frames > 0, hop = seg_len/2) with the ring
+ * stored per pixel tile of the chunk kernel, [slot][tile][row][tile pixels],
+ * instead of per frame: a tile's chunk is then contiguous in memory, so the
+ * chunk kernel needs a few address translations per chunk instead of one per
+ * frame (large frames, e.g. 1024^2 pixels, otherwise miss the translation
+ * caches on most loads). Pushes only: tacaw_ingest_frames needs the per-frame
+ * layout and fails with STATE on such a plan. */
+#define TACAW_FLAG_TILED_RING 2
 
 typedef struct {
   int32_t n_segments;     /* N_s                                                     */

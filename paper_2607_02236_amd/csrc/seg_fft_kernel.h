@@ -72,6 +72,8 @@ struct FftShape<200> {
 // all loads use uniform row bases and the frames to count in the mean sum are
 // known per n1 at compile time. The general variant also reads the ring, takes
 // any hop and decides per lane.
+// MODE 4: MODE 2 with the ring stored per pixel tile, [slot][tile][row][W], so
+// that a tile's chunk is contiguous (few address translations per chunk).
 // MODE 0: general (any hop; frames before the push from the ring, per lane);
 // MODE 1: whole-series variant reading the push buffer; MODE 2: whole-series
 // variant reading every frame from the ring (deferred streaming); MODE 3: MODE 1
@@ -88,7 +90,8 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
     __attribute__((amdgpu_waves_per_eu(TACAW_WAVES_PER_EU)))
     seg_fft_kernel(const SegArgs a) {
   constexpr bool LEAN = MODE != 0;
-  constexpr bool RING = MODE == 2;
+  constexpr bool TILED = MODE == 4;
+  constexpr bool RING = MODE == 2 || TILED;
   constexpr bool NARROW = MODE == 3;
   constexpr int N1 = FftShape<L>::N1;
   constexpr int W = FftShape<L>::W;
@@ -164,6 +167,10 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
 
   // LEAN: raw samples of the next chunk, loaded one chunk ahead (software prefetch)
   InT pre[LEAN ? N1 : 1];
+  // MODE 4: the ring is stored per pixel tile ([slot][tile][row][W]), so a row
+  // group of a tile is N2 consecutive rows of W pixels
+  const uint32_t tiled_off = (uint32_t)(((int64_t)n2 * W + px) * ESZ);
+  constexpr uint32_t tiled_bytes = (uint32_t)(N2 * W * ESZ);
   // MODE 3: a chunk's frames lie within 2 GiB of its first row
   const uint32_t chunk_bytes =
       NARROW ? (uint32_t)((int64_t)(L - N2) * row_bytes + (int64_t)group_bytes) : 0u;
@@ -184,6 +191,12 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
       row += N2 * n1;
       if (row >= D) row -= D;
       const int64_t slot = (a.probe0 + ii) % a.n_slots;
+      if constexpr (TILED) {
+        int64_t tb = (int64_t)W * ESZ;  // bytes per tile row, formed next to the load
+        asm volatile("" : "+s"(tb));
+        rb = (const char*)a.ring + ((slot * a.ring_tiles + tile) * D + row) * tb;
+        return buffer_load<InT>(rb, tiled_bytes, tiled_off);
+      }
       int64_t rbytes = row_bytes;  // formed next to the load (see the push case below)
       asm volatile("" : "+s"(rbytes));
       rb = (const char*)a.ring + (slot * D + row) * rbytes;

@@ -92,7 +92,7 @@ hipError_t launch_ref_mean(const void* in, int in_dtype, int64_t pstride, int64_
 }
 
 // ring[slot][f % D][k] = in[i][f - push_begin][k] for f in [f_lo, f_hi); each
-// thread copies 16 bytes (two complex64 or one complex128 element)
+// thread copies 16 bytes (two complex64 or one complex128 element).
 template <typename InT>
 __global__ void ring_store_kernel(const InT* in, int64_t pstride, int64_t fstride, int32_t nx,
                                   int64_t rs, int64_t push_begin, int64_t f_lo, int32_t n_f,
@@ -112,13 +112,60 @@ __global__ void ring_store_kernel(const InT* in, int64_t pstride, int64_t fstrid
     if (k0 + v < n_k) dst[k0 + v] = src[pix_off(k0 + v, nx, rs)];
 }
 
+// The same into a ring stored per pixel tile: element (slot, row, k) at
+// ((slot * n_tiles + k / W) * D + row) * W + k % W. A block copies R consecutive
+// frames (R = 8, or the largest power of two dividing D; the first frame aligned
+// to R in absolute frame index) of 256 V / R pixels, so it reads R runs of 256 V / R pixels and
+// writes R consecutive rows, R W elements in a row, of each of its tiles: long
+// runs on both sides instead of one tile row (64 bytes at W = 8) per tile.
+template <typename InT>
+__global__ void ring_store_tiled_kernel(const InT* in, int64_t pstride, int64_t fstride,
+                                        int32_t nx, int64_t rs, int64_t push_begin, int64_t f_lo,
+                                        int64_t f_hi, int32_t R, int32_t probe0, int32_t n_slots,
+                                        int64_t depth, int32_t n_k, int32_t tile_w,
+                                        int32_t n_tiles, InT* ring) {
+  constexpr int V = 16 / (int)sizeof(InT);  // elements per thread
+  const int tpr = 256 / R;                   // threads per frame
+  const int r = threadIdx.x / tpr;
+  const int64_t k0 = ((int64_t)blockIdx.x * tpr + threadIdx.x % tpr) * V;
+  const int64_t f = (f_lo - f_lo % R) + (int64_t)blockIdx.y * R + r;
+  const int i = blockIdx.z;
+  if (k0 >= n_k || f < f_lo || f >= f_hi) return;
+  const int slot = (probe0 + i) % n_slots;
+  const InT* src = in + (int64_t)i * pstride + (f - push_begin) * fstride;
+  const int64_t t = k0 / tile_w;  // tile_w is a multiple of V: the V elements share a tile row
+  InT* dst = ring + (((int64_t)slot * n_tiles + t) * depth + (f % depth)) * tile_w + (k0 - t * tile_w);
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+    if (k0 + v < n_k) dst[v] = src[pix_off(k0 + v, nx, rs)];
+}
+
 hipError_t launch_ring_store(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
                              int32_t nx, int64_t rs, int64_t push_begin, int64_t f_lo,
                              int64_t f_hi, int32_t probe0, int32_t n_probes, int32_t n_slots,
-                             int64_t depth, int32_t n_k, void* ring, hipStream_t st) {
+                             int64_t depth, int32_t n_k, int32_t tile_w, void* ring,
+                             hipStream_t st) {
   const int64_t nf = f_hi - f_lo;
   if (nf <= 0) return hipSuccess;
   const int V = in_dtype == 1 ? 1 : 2;
+  if (tile_w > 0) {
+    int R = 8;  // rows per block: the largest power of two <= 8 that divides D
+    while (depth % R != 0) R /= 2;
+    if (tile_w % V != 0) return hipErrorInvalidValue;
+    const int32_t n_tiles = (n_k + tile_w - 1) / tile_w;
+    const int64_t fb = f_lo - f_lo % R;
+    dim3 g((unsigned)((n_k + (256 / R) * V - 1) / ((256 / R) * V)),
+           (unsigned)((f_hi - fb + R - 1) / R), n_probes);
+    if (in_dtype == 1)
+      hipLaunchKernelGGL(ring_store_tiled_kernel<double2>, g, dim3(256), 0, st, (const double2*)in,
+                         pstride, fstride, nx, rs, push_begin, f_lo, f_hi, R, probe0, n_slots,
+                         depth, n_k, tile_w, n_tiles, (double2*)ring);
+    else
+      hipLaunchKernelGGL(ring_store_tiled_kernel<float2>, g, dim3(256), 0, st, (const float2*)in,
+                         pstride, fstride, nx, rs, push_begin, f_lo, f_hi, R, probe0, n_slots,
+                         depth, n_k, tile_w, n_tiles, (float2*)ring);
+    return hipGetLastError();
+  }
   dim3 g((unsigned)((n_k + 256 * V - 1) / (256 * V)), (unsigned)nf, n_probes);
   if (in_dtype == 1)
     hipLaunchKernelGGL(ring_store_kernel<double2>, g, dim3(256), 0, st, (const double2*)in,

@@ -1,5 +1,6 @@
 // Launchers of the ring-resident whole-series variant of the fused chunk kernel
-// (deferred streaming: every frame of the launch's chunks is read from the ring).
+// (deferred streaming: every frame of the launch's chunks is read from the ring, stored
+// per frame or per pixel tile).
 #include "seg_fft_kernel.h"
 
 namespace tacaw {
@@ -7,10 +8,17 @@ namespace tacaw {
 template <int L, typename InT, bool SUB64>
 static hipError_t launch_ring_t(const SegArgs& a, int n_tiles, hipStream_t st) {
   constexpr int NT = FftShape<L>::W * (L / FftShape<L>::N1);
-  if (a.n_det > 0)
-    hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, 2>), dim3(n_tiles), dim3(NT), 0, st, a);
-  else
-    hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, false, 2>), dim3(n_tiles), dim3(NT), 0, st, a);
+  if (a.ring_tiles > 0) {
+    if (a.n_det > 0)
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, 4>), dim3(n_tiles), dim3(NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, false, 4>), dim3(n_tiles), dim3(NT), 0, st, a);
+  } else {
+    if (a.n_det > 0)
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, 2>), dim3(n_tiles), dim3(NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, false, 2>), dim3(n_tiles), dim3(NT), 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -30,6 +30,8 @@ struct SegArgs {
   int64_t ring_depth;      // D (>= L, < 2^30)
   int32_t ring_row_lo;     // (s_lo * hop) mod D: ring row of the launch's first chunk
   int32_t from_ring;       // whole-series variant: every chunk is read from the ring
+  int32_t ring_tiles;      // > 0: the ring is stored per pixel tile, [n_slots][ring_tiles][D][W]
+                           // (W = the chunk kernel's tile width); 0: [n_slots][D][n_k]
   int32_t n_slots;
   int32_t n_k;
   int32_t probe0;          // first probe of the push
@@ -89,7 +91,8 @@ hipError_t launch_ref_mean(const void* in, int in_dtype, int64_t pstride, int64_
 hipError_t launch_ring_store(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
                              int32_t nx, int64_t rs, int64_t push_begin, int64_t f_lo,
                              int64_t f_hi, int32_t probe0, int32_t n_probes, int32_t n_slots,
-                             int64_t depth, int32_t n_k, void* ring, hipStream_t st);
+                             int64_t depth, int32_t n_k, int32_t tile_w, void* ring,
+                             hipStream_t st);
 // det_off[d] .. det_off[d + 1]: the dpart slots of detector d (n_det + 1 entries)
 struct DetSlots {
   int32_t off[kMaxDet + 1];

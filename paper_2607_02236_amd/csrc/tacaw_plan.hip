@@ -198,6 +198,7 @@ struct tacaw_plan_s {
   int64_t D = 0;                      // ring depth (frames per slot)
   int64_t rs = 0, span = 0;           // input pixel-row stride and elements spanned per frame
   bool deferred = false;              // deferred ring mode (ring_frames > seg_len)
+  bool tiled = false;                 // the ring is stored per pixel tile
   std::vector<int> s_done;            // deferred mode: chunks processed per probe
   bool s_fresh = true;                // no chunk launch since the last reset: S is undefined
   bool ingest_open = false;           // tacaw_ingest_frames handed out ring rows
@@ -275,6 +276,7 @@ static int run_chunks(tacaw_plan_t P, const void* src, int64_t pstride, int64_t 
   g.ring_depth = P->D;
   g.ring_row_lo = (int32_t)(((int64_t)s_lo * P->H) % P->D);
   g.from_ring = from_ring ? 1 : 0;
+  g.ring_tiles = P->tiled ? P->n_tiles : 0;
   g.n_slots = P->n_slots;
   g.n_k = P->n_k;
   g.probe0 = probe0;
@@ -369,8 +371,12 @@ static int claim_slots(tacaw_plan_t P, int probe0, int n_probes) {
       return fail(TACAW_ERR_STATE, "ring capacity exceeded: too many probes in flight");
   }
   if (!P->ring) {
-    const int64_t rb = (int64_t)P->n_slots * P->D * P->n_k * P->esz;
+    // tiled: whole tiles (the last one padded), zeroed once so that the padding
+    // pixels, which no store writes, read as 0
+    const int64_t px = P->tiled ? (int64_t)P->n_tiles * P->W : P->n_k;
+    const int64_t rb = (int64_t)P->n_slots * P->D * px * P->esz;
     TRY(P->alloc(&P->ring, rb, "frame ring"));
+    if (P->tiled) TRY(hip_check(launch_fill_zero(P->ring, rb, P->st), "ring padding"));
   }
   return TACAW_OK;
 }
@@ -445,6 +451,12 @@ int tacaw_plan_check(const tacaw_plan_desc* d) {
     if (d->transform != TACAW_FFT_F32)
       return fail(TACAW_ERR_UNSUPPORTED, "deferred ring mode needs the FFT transform");
   }
+  if (d->flags & TACAW_FLAG_TILED_RING) {
+    if (d->ring_frames == 0)
+      return fail(TACAW_ERR_INVALID_ARG, "a tiled ring needs the deferred ring mode (ring_frames > 0)");
+    if (2 * d->hop != d->seg_len)
+      return fail(TACAW_ERR_UNSUPPORTED, "a tiled ring needs hop = seg_len / 2");
+  }
   const int64_t n_k = (int64_t)d->ny * d->nx;
   const int64_t n_om = d->omega_half > 0 ? 2 * (int64_t)d->omega_half + 1 : d->seg_len;
   const int64_t need = n_om * n_k * 8 + (int64_t)d->n_probe * n_k * 80 +
@@ -476,6 +488,7 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   P->cursor.assign(d->n_probe, 0);
   P->s_done.assign(d->n_probe, 0);
   P->deferred = d->ring_frames > 0;
+  P->tiled = (d->flags & TACAW_FLAG_TILED_RING) != 0;
   P->rs = d->k_row_stride > 0 ? d->k_row_stride : d->nx;
   P->span = (int64_t)(d->ny - 1) * P->rs + d->nx;
   P->D = P->deferred ? d->ring_frames : P->L;
@@ -779,7 +792,7 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
     if (need_ring_write)
       TRY(hip_check(launch_ring_store(frames, P->d.in_dtype, pstride, fstride, P->d.nx, P->rs, a,
                                       keep_lo, keep_hi, probe0, n_probes, P->n_slots, P->D,
-                                      P->n_k, P->ring, P->st),
+                                      P->n_k, 0, P->ring, P->st),
                     "ring store"));
   } else {
     // deferred: the push is copied into the ring; completed chunks run from there
@@ -787,7 +800,8 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
     if (need_ring_write)
       TRY(hip_check(launch_ring_store(frames, P->d.in_dtype, pstride, fstride, P->d.nx, P->rs, a,
                                       a, std::min<int64_t>(b, P->n_used), probe0, n_probes,
-                                      P->n_slots, P->D, P->n_k, P->ring, P->st),
+                                      P->n_slots, P->D, P->n_k, P->tiled ? P->W : 0, P->ring,
+                                      P->st),
                     "ring store"));
     TRY(deferred_finish(P, probe0, n_probes, b));
   }
@@ -803,6 +817,7 @@ int tacaw_ingest_frames(tacaw_plan_t P, int32_t probe0, int32_t n_probes, int64_
   *d_dst = nullptr;
   if (P->state != 0) return fail(TACAW_ERR_STATE, "plan is finalized");
   if (!P->deferred) return fail(TACAW_ERR_STATE, "ingest needs the deferred ring mode");
+  if (P->tiled) return fail(TACAW_ERR_STATE, "ingest needs the per-frame ring layout (no TACAW_FLAG_TILED_RING)");
   if (P->ingest_open) return fail(TACAW_ERR_STATE, "the previous ingest is not committed");
   if (n_probes < 1 || probe0 < 0 || probe0 + (int64_t)n_probes > P->d.n_probe)
     return fail(TACAW_ERR_SHAPE, "probe range outside the plan");

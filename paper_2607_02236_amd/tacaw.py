@@ -13,6 +13,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
+FLAG_TIME_KERNELS = 1  # TACAW_FLAG_TIME_KERNELS
+FLAG_TILED_RING = 2  # TACAW_FLAG_TILED_RING
 LIB_PATH = os.environ.get("TACAW_LIB") or os.path.join(_HERE, "libtacaw.so")
 
 OK = 0
@@ -149,14 +151,15 @@ class Plan:
     """One spectral reduction: push exit-wave frames, finalize, read spectra.
 
     masks: optional torch float64 CUDA tensor [n_det, ny, nx] (enables the fused
-    per-probe detector spectra).
+    per-probe detector spectra). ring_frames > seg_len: deferred streaming ring;
+    tiled_ring: store that ring per pixel tile (pushes only, hop = seg_len / 2).
     """
 
     def __init__(self, n_probe, ny, nx, n_frames, seg_len, hop=None, window="hann",
                  window_param=1.0, mean_mode="global", transform="fft", in_dtype="c64",
                  probe_reduce="mean", dt_fs=5.0, masks=None, max_probes_in_flight=0,
                  stream=None, time_kernels=False, temperature_K=0.0, omega_half=0,
-                 ring_frames=0, k_row_stride=0):
+                 ring_frames=0, k_row_stride=0, tiled_ring=False):
         self.handle = None
         hop = seg_len // 2 if hop is None else hop
         self.n_probe, self.ny, self.nx = int(n_probe), int(ny), int(nx)
@@ -177,7 +180,9 @@ class Plan:
         self.stream, sptr = _stream_ptr(stream)
         self.desc = make_desc(n_probe, ny, nx, n_frames, seg_len, hop, window, window_param,
                               mean_mode, transform, in_dtype, probe_reduce, dt_fs, n_det, mptr,
-                              max_probes_in_flight, 1 if time_kernels else 0, temperature_K,
+                              max_probes_in_flight,
+                              (FLAG_TIME_KERNELS if time_kernels else 0)
+                              | (FLAG_TILED_RING if tiled_ring else 0), temperature_K,
                               omega_half=omega_half, ring_frames=ring_frames,
                               k_row_stride=k_row_stride)
         self.row_stride = int(k_row_stride) or self.nx

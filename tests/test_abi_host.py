@@ -64,6 +64,8 @@ def _ok(**over):
     (dict(ring_frames=160), "INVALID_ARG"),   # multiple of seg_len / 2
     (dict(ring_frames=256, transform="gemm_f16x3"), "UNSUPPORTED"),
     (dict(omega_half=64), "INVALID_ARG"),  # must be < seg_len / 2
+    (dict(flags=2), "INVALID_ARG"),                           # tiled ring without a ring
+    (dict(flags=2, ring_frames=256, hop=128, n_frames=512), "UNSUPPORTED"),  # needs hop = L/2
 ])
 def test_descriptor_validation_errors(over, kind):
     from paper_2607_02236_amd import tacaw
@@ -86,6 +88,7 @@ def test_valid_descriptors_pass():
     tacaw.check_desc(**_ok(transform="gemm_bf16x3"))
     tacaw.check_desc(**_ok(omega_half=63))
     tacaw.check_desc(**_ok(ring_frames=192))
+    tacaw.check_desc(**_ok(ring_frames=192, flags=tacaw.FLAG_TILED_RING))
     tacaw.check_desc(**_ok(k_row_stride=40))
     tacaw.check_desc(**_ok(seg_len=200, hop=100, n_frames=3200, dt_fs=15.0, omega_half=90))
     tacaw.check_desc(**_ok(omega_half=1, transform="gemm_f16x3", temperature_K=50.0))

@@ -364,6 +364,35 @@ def test_deferred_ring_mode_matches_immediate_and_oracle(tacaw, L, H, NT, D, pus
     check(g, oracle_all(psi, L, H, masks=masks), label=f"deferred L={L} H={H} D={D}")
 
 
+@pytest.mark.parametrize("L,H,NT,D,ny,nx,dtype,pushes", [
+    (128, 64, 640, 192, 9, 7, "c64", [64, 1, 63, 64, 64, 40, 24, 64, 64, 64, 64, 64]),
+    (1024, 512, 2560, 2048, 5, 11, "c64", [512] * 5),     # 8-pixel tiles, last one padded
+    (200, 100, 900, 300, 6, 9, "c64", [100] * 9),         # 32-pixel tiles
+    (256, 128, 896, 512, 3, 13, "c128", [128] * 7),       # one complex128 element per store lane
+])
+def test_tiled_ring_matches_per_frame_ring_and_oracle(tacaw, L, H, NT, D, ny, nx, dtype, pushes):
+    # the ring stored per pixel tile ([slot][tile][row][W]) gives the per-frame
+    # ring's results bit for bit (same chunk arithmetic, other addresses)
+    spec = T.SeriesSpec(3, NT, ny, nx, dtype=dtype, seed=D + L + 7, model="lines", n_terms=8)
+    psi = T.generate(spec)
+    masks = T.standard_masks(ny, nx, scale=0.06)
+    masks[3] = np.random.default_rng(13).random((ny, nx))
+    kw = dict(pushes=pushes, probe_batches=[(0, 2), (2, 3)], max_probes_in_flight=2,
+              ring_frames=D)
+    ref = run_gpu(tacaw, psi, L, H, masks, **kw)
+    g = run_gpu(tacaw, psi, L, H, masks, tiled_ring=True, **kw)
+    assert np.array_equal(g["S"], ref["S"]) and np.array_equal(g["Dp"], ref["Dp"])
+    check(g, oracle_all(psi, L, H, masks=masks), label=f"tiled ring L={L} D={D} {dtype}")
+
+
+def test_tiled_ring_rejects_ingest(tacaw):
+    plan = tacaw.Plan(1, 4, 4, 640, 128, 64, ring_frames=256, tiled_ring=True)
+    with pytest.raises(tacaw.TacawError) as e:
+        plan.ingest(64)
+    assert e.value.kind == "STATE"
+    plan.close()
+
+
 def test_deferred_ring_mode_errors(tacaw):
     psi = torch.ones((1, 640, 4, 4), dtype=torch.complex64, device="cuda")
     plan = tacaw.Plan(1, 4, 4, 640, 128, 64, ring_frames=256)
