@@ -114,7 +114,7 @@ __global__ void ring_store_kernel(const InT* in, int64_t pstride, int64_t fstrid
 
 // The same into a ring stored per pixel tile: element (slot, row, k) at
 // ((slot * n_tiles + k / W) * D + row) * W + k % W. A block copies R consecutive
-// frames (R = 8, or the largest power of two dividing D; the first frame aligned
+// frames (R = 16, or the largest power of two dividing D; the first frame aligned
 // to R in absolute frame index) of 256 V / R pixels, so it reads R runs of 256 V / R pixels and
 // writes R consecutive rows, R W elements in a row, of each of its tiles: long
 // runs on both sides instead of one tile row (64 bytes at W = 8) per tile.
@@ -149,7 +149,10 @@ hipError_t launch_ring_store(const void* in, int in_dtype, int64_t pstride, int6
   if (nf <= 0) return hipSuccess;
   const int V = in_dtype == 1 ? 1 : 2;
   if (tile_w > 0) {
-    int R = 8;  // rows per block: the largest power of two <= 8 that divides D
+#ifndef TACAW_RING_ROWS
+#define TACAW_RING_ROWS 16  // frames per block of the tiled ring store (tuning parameter)
+#endif
+    int R = TACAW_RING_ROWS;  // halved until it divides D
     while (depth % R != 0) R /= 2;
     if (tile_w % V != 0) return hipErrorInvalidValue;
     const int32_t n_tiles = (n_k + tile_w - 1) / tile_w;
