@@ -30,6 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# sources of the chunk kernel (the counter summary is valid only for these bytes)
+KERNEL_SOURCES = ["seg_fft_kernel.h", "regfft.h", "buffer_io.h", "tacaw_internal.h", "tacaw_fft.hip"]
 METRIC = "exit-wave GB/s -> S(k,omega) (frac. HBM peak); FFT vs MFMA DFT-GEMM at fixed err"
 
 
@@ -266,7 +268,7 @@ def main():
     m_rows = (2 * n_om + 31) // 32 * 32  # GEMM rows computed (window rows, padded to 32)
     gemm_flops = 3 * 2 * m_rows * 2 * L * n_seg * spec.n_probe * spec.n_k  # executed, 3 products
     csrc = os.path.join(ROOT, "paper_2607_02236_amd", "csrc")
-    ksrc = [os.path.join(csrc, f) for f in ("seg_fft_kernel.h", "regfft.h", "tacaw_fft.hip")] \
+    ksrc = [os.path.join(csrc, f) for f in KERNEL_SOURCES] \
         if args.form == "fft" else [os.path.join(csrc, "tacaw_gemm.hip")]
     out = {
         "metric": METRIC,
@@ -303,9 +305,10 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "kernel_ms": round(k_ms, 4),
             "traffic": traffic_from_profiles(ksrc),
-            "note": "traffic ~1.05x algorithmic: the chunk kernel is bound by non-packed FP32 "
-                    "VALU issue (about 44 instructions per point and transform, two transforms "
-                    "per element at 50% overlap; 39.3 T lane-ops/s peak), not by HBM",
+            "note": "HBM traffic is ~1.02x the algorithmic bytes; the chunk kernel is bound by "
+                    "non-packed FP32 VALU issue and its latency at two waves per SIMD (about 32 "
+                    "VALU instructions per point and transform, two transforms per element at "
+                    "50% overlap, VALU busy ~67%; peak 39.3 T lane-ops/s), not by HBM",
         },
     }
     if gradient:

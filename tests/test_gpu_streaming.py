@@ -19,19 +19,20 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
-@pytest.mark.parametrize("n_probe,batch,grid,chunk,ring", [
-    (4, 2, 256, 256, 0),        # quick: 256 x 256 grid
-    (16, 4, 1024, 256, 0),      # one GPU's share of the 256-probe scan at the full grid
-    (16, 4, 1024, 256, 2048),   # the same, deferred: chunks wait in a 2048-frame ring
+@pytest.mark.parametrize("n_probe,batch,grid,chunk,ring,tiled", [
+    (4, 2, 256, 256, 0, False),        # quick: 256 x 256 grid
+    (16, 4, 1024, 256, 0, False),      # one GPU's share of the 256-probe scan at the full grid
+    (16, 4, 1024, 256, 2048, False),   # the same, deferred: chunks wait in a 2048-frame ring
+    (16, 4, 1024, 256, 2048, True),    # the same with the ring stored per pixel tile
 ])
-def test_streaming_pushes_match_oracle(n_probe, batch, grid, chunk, ring):
+def test_streaming_pushes_match_oracle(n_probe, batch, grid, chunk, ring, tiled):
     from paper_2607_02236_amd import tacaw
 
     spec = T.config_streaming(n_probe=n_probe, n_frames=4096, ny=grid, nx=grid)
     L, H = 1024, 512
     masks = torch.from_numpy(T.standard_masks(grid, grid, scale=grid / 256)).cuda()
     plan = tacaw.Plan(n_probe, grid, grid, spec.n_frames, L, H, masks=masks,
-                      max_probes_in_flight=batch, ring_frames=ring)
+                      max_probes_in_flight=batch, ring_frames=ring, tiled_ring=tiled)
     buf = torch.empty((batch, chunk, grid, grid), dtype=torch.complex64, device="cuda")
     for p0 in range(0, n_probe, batch):
         for f0 in range(0, spec.n_frames, chunk):
@@ -53,7 +54,8 @@ def test_streaming_pushes_match_oracle(n_probe, batch, grid, chunk, ring):
     Dref = torch.einsum("jk,mk->jm", masks.reshape(masks.shape[0], -1), S.reshape(L, -1))
     eD = max(rel(D[j].cpu(), Dref[j].cpu()) for j in range(D.shape[0]))
     eDp = rel(Dp.mean(dim=1).cpu(), D.cpu())  # probe mean of per-probe spectra = D
-    print(f"streaming {n_probe} probes {grid}^2 ring {ring}: S(sampled) {e:.2e} D {eD:.2e} "
+    print(f"streaming {n_probe} probes {grid}^2 ring {ring}{' tiled' if tiled else ''}: "
+          f"S(sampled) {e:.2e} D {eD:.2e} "
           f"mean(Dp) {eDp:.2e}")
     assert e <= 1e-5 and eD <= 1e-12 and eDp <= 1e-12
     plan.close()
