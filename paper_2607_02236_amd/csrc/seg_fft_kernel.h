@@ -68,9 +68,9 @@ struct FftShape<200> {
   static constexpr int N1 = 10, W = 32;
 };
 
-// LEAN: every chunk of the launch lies inside the push buffer and H = L/2, so
-// all loads use uniform row bases and the frames to count in the mean sum are
-// known per n1 at compile time. The general variant also reads the ring, takes
+// LEAN: every chunk of the launch lies inside the push buffer and H = L/2 or
+// H = L, so all loads use uniform row bases and the frames to count in the mean
+// sum are known per n1 at compile time. The general variant also reads the ring, takes
 // any hop and decides per lane.
 // MODE 4: MODE 2 with the ring stored per pixel tile, [slot][tile][row][W], so
 // that a tile's chunk is contiguous (few address translations per chunk).
@@ -293,7 +293,8 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
       using C3 = std::integral_constant<int, 3>;
 
       if constexpr (LEAN) {
-        // chunk s: frames with t >= L/2 (n1 >= HALF) are new; t < L/2 are new only for s = 0
+        // H = L/2, chunk s: frames with t >= L/2 (n1 >= HALF) are new; t < L/2 are new
+        // only for s = 0. H = L: every frame of every chunk is new.
         auto take_pre = [&](int lo, auto cmode) {
 #pragma unroll
           for (int n1 = 0; n1 < N1; ++n1)
@@ -306,7 +307,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
           else take_pre(HALF, C0{});
         } else if (!track) {
           take_pre(0, C0{});
-        } else if (s == 0) {
+        } else if (s == 0 || !half_hop) {
           take_pre(0, C1{});
         } else {
           take_pre(0, C3{});
@@ -318,7 +319,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
           const int ss = next_chunk ? s + 1 : a.s_lo;
 #pragma unroll
           for (int n1 = 0; n1 < N1; ++n1)
-            if (n1 >= HALF || !next_chunk) pre[n1] = fetch_at(ii, ss, n1);
+            if (n1 >= HALF || !next_chunk || !half_hop) pre[n1] = fetch_at(ii, ss, n1);
         }
       } else if (have_kept && half_hop) {
         // the kept half was counted in the previous chunk; the new half all counts
@@ -345,7 +346,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
       }
 #pragma unroll
       for (int n1 = HALF; n1 < N1; ++n1) kept[n1 - HALF] = v[n1];
-      have_kept = true;
+      have_kept = !LEAN || half_hop;  // (the general variant also tests half_hop itself)
 
       // window (table stored per thread: s_win[n2 * N1 + n1] = w(N2 n1 + n2))
 #pragma unroll

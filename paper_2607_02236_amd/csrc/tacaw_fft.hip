@@ -8,7 +8,8 @@ namespace tacaw {
 template <int L, typename InT, bool SUB64>
 static hipError_t launch_t(const SegArgs& a, int n_tiles, hipStream_t st) {
   constexpr int NT = FftShape<L>::W * (L / FftShape<L>::N1);
-  const bool lean = (2 * a.hop == L) && !a.from_ring && (int64_t)a.s_lo * a.hop >= a.push_begin;
+  const bool lean = (2 * a.hop == L || a.hop == L) && !a.from_ring &&
+                    (int64_t)a.s_lo * a.hop >= a.push_begin;
   // one descriptor per chunk when a chunk's frames span less than 2 GiB
   const int64_t span = pix_off((int64_t)a.n_k - 1, a.nx, a.row_stride) + 1;
   const bool narrow =

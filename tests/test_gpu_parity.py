@@ -110,6 +110,9 @@ def test_plain_one_probe_complex128(tacaw):
     (200, 100, 700, 9, 13, 2),     # prime-factor 10-point passes, ragged tiles of 32
     (200, 200, 650, 5, 5, 2),      # no overlap, dropped tail
     (200, 64, 600, 7, 7, 1),       # general hop
+    (256, 256, 1100, 13, 17, 3),   # no overlap, several probes per tile (whole-series variant)
+    (1024, 1024, 3100, 4, 9, 2),
+    (128, 128, 1000, 6, 5, 3),
 ])
 def test_lines_model_multi_probe(tacaw, L, H, NT, ny, nx, P):
     spec = T.SeriesSpec(P, NT, ny, nx, dtype="c64", seed=L + H, model="lines", n_terms=8,
