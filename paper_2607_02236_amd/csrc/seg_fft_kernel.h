@@ -85,11 +85,13 @@ struct FftShape<200> {
 #ifndef TACAW_WAVES_PER_EU
 #define TACAW_WAVES_PER_EU 1  // minimum waves per SIMD the register allocation must allow
 #endif
-template <int L, typename InT, bool SUB64, bool DP, int MODE>
+// FULL (whole-series variants only): hop = L, no overlap; otherwise hop = L/2 there.
+template <int L, typename InT, bool SUB64, bool DP, int MODE, bool FULL = false>
 __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
     __attribute__((amdgpu_waves_per_eu(TACAW_WAVES_PER_EU)))
     seg_fft_kernel(const SegArgs a) {
   constexpr bool LEAN = MODE != 0;
+  static_assert(LEAN || !FULL, "hop = L is a whole-series variant");
   constexpr bool TILED = MODE == 4;
   constexpr bool RING = MODE == 2 || TILED;
   constexpr bool NARROW = MODE == 3;
@@ -307,7 +309,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
           else take_pre(HALF, C0{});
         } else if (!track) {
           take_pre(0, C0{});
-        } else if (s == 0 || !half_hop) {
+        } else if (s == 0 || FULL) {
           take_pre(0, C1{});
         } else {
           take_pre(0, C3{});
@@ -319,7 +321,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
           const int ss = next_chunk ? s + 1 : a.s_lo;
 #pragma unroll
           for (int n1 = 0; n1 < N1; ++n1)
-            if (n1 >= HALF || !next_chunk || !half_hop) pre[n1] = fetch_at(ii, ss, n1);
+            if (n1 >= HALF || !next_chunk || FULL) pre[n1] = fetch_at(ii, ss, n1);
         }
       } else if (have_kept && half_hop) {
         // the kept half was counted in the previous chunk; the new half all counts
@@ -344,9 +346,11 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
           else load_range(0, fetch_any, C2{});
         }
       }
+      if constexpr (!FULL) {
 #pragma unroll
-      for (int n1 = HALF; n1 < N1; ++n1) kept[n1 - HALF] = v[n1];
-      have_kept = !LEAN || half_hop;  // (the general variant also tests half_hop itself)
+        for (int n1 = HALF; n1 < N1; ++n1) kept[n1 - HALF] = v[n1];
+        have_kept = true;  // (the general variant also tests half_hop itself)
+      }
 
       // window (table stored per thread: s_win[n2 * N1 + n1] = w(N2 n1 + n2))
 #pragma unroll

@@ -5,6 +5,22 @@
 
 namespace tacaw {
 
+template <int L, typename InT, bool SUB64, bool FULL>
+static void launch_lean(const SegArgs& a, bool narrow, int n_tiles, hipStream_t st) {
+  constexpr int NT = FftShape<L>::W * (L / FftShape<L>::N1);
+  if (narrow) {
+    if (a.n_det > 0)
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, 3, FULL>), dim3(n_tiles), dim3(NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, false, 3, FULL>), dim3(n_tiles), dim3(NT), 0, st, a);
+  } else {
+    if (a.n_det > 0)
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, 1, FULL>), dim3(n_tiles), dim3(NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, false, 1, FULL>), dim3(n_tiles), dim3(NT), 0, st, a);
+  }
+}
+
 template <int L, typename InT, bool SUB64>
 static hipError_t launch_t(const SegArgs& a, int n_tiles, hipStream_t st) {
   constexpr int NT = FftShape<L>::W * (L / FftShape<L>::N1);
@@ -14,16 +30,9 @@ static hipError_t launch_t(const SegArgs& a, int n_tiles, hipStream_t st) {
   const int64_t span = pix_off((int64_t)a.n_k - 1, a.nx, a.row_stride) + 1;
   const bool narrow =
       ((int64_t)(L - 1) * a.fstride + span) * (int64_t)sizeof(InT) < ((int64_t)1 << 31);
-  if (lean && narrow) {
-    if (a.n_det > 0)
-      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, 3>), dim3(n_tiles), dim3(NT), 0, st, a);
-    else
-      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, false, 3>), dim3(n_tiles), dim3(NT), 0, st, a);
-  } else if (lean) {
-    if (a.n_det > 0)
-      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, 1>), dim3(n_tiles), dim3(NT), 0, st, a);
-    else
-      hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, false, 1>), dim3(n_tiles), dim3(NT), 0, st, a);
+  if (lean) {
+    if (a.hop == L) launch_lean<L, InT, SUB64, true>(a, narrow, n_tiles, st);
+    else launch_lean<L, InT, SUB64, false>(a, narrow, n_tiles, st);
   } else {
     if (a.n_det > 0)
       hipLaunchKernelGGL((seg_fft_kernel<L, InT, SUB64, true, 0>), dim3(n_tiles), dim3(NT), 0, st, a);
