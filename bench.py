@@ -30,8 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# sources of the chunk kernel (the counter summary is valid only for these bytes)
+# sources of the chunk kernel and of the adjoint (a counter summary is valid only for these bytes)
 KERNEL_SOURCES = ["seg_fft_kernel.h", "regfft.h", "buffer_io.h", "tacaw_internal.h", "tacaw_fft.hip"]
+ADJOINT_SOURCES = ["tacaw_adjoint.hip", "regfft.h", "buffer_io.h", "tacaw_internal.h"]
 METRIC = "exit-wave GB/s -> S(k,omega) (frac. HBM peak); FFT vs MFMA DFT-GEMM at fixed err"
 
 
@@ -48,10 +49,10 @@ def source_sha(paths):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_src):
+def traffic_from_profiles(kernel_src, name="seg_fft_L512_64probes_counters.json"):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "seg_fft_L512_64probes_counters.json")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     try:
@@ -317,7 +318,9 @@ def main():
         out["roofline"] = {
             "bound": "hbm", "kernel": "bwd_kernel", "achieved": round(ach_b, 2),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach_b / HBM_PEAK_GBS, 4),
-            "kernel_ms": round(t_b, 4), "traffic": None,
+            "kernel_ms": round(t_b, 4),
+            "traffic": traffic_from_profiles([os.path.join(csrc, f) for f in ADJOINT_SOURCES],
+                                             "bwd_kernel_L512_16probes_counters.json"),
             "forward_chunk_kernel_ms": round(k_ms, 4),
             "note": "adjoint launch (bwd_kernel and the window-parameter reduction): reads "
                     "psi once and writes dL/dpsi once (2 x exit-wave bytes); it recomputes "

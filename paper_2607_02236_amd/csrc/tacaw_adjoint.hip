@@ -130,6 +130,9 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
     int r = m + a.roi_half;  // output row of bin m
     if (r >= L) r -= L;
     const int n_om = a.n_om;
+    // the row passes through an empty asm so that the 16 bins' addresses are
+    // formed on each call instead of being hoisted out of the probe loop (and spilled)
+    asm volatile("" : "+v"(r));
     double g = 0.0;
     if (r < n_om) {
       if (a.gS) g += a.kappa_S * a.gS[(int64_t)r * n_k + kc];
@@ -211,9 +214,14 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
         return make_float2((float)((double)x.x - mu.x), (float)((double)x.y - mu.y));
       };
       float2 v[N1];
+      // DW (complex64): the centred samples stay in registers for the r-derivative
+      // (re-reading them at the end of the chunk missed the L2 and doubled the reads)
+      constexpr bool KEEP_Z = DW && sizeof(InT) == 8 && L <= 512;
+      float2 zk[KEEP_Z ? N1 : 1];
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) {
         const float2 z = centre(pre[n1]);
+        if constexpr (KEEP_Z) zk[n1] = z;
         const float w = s_win[n2 * N1 + n1];
         v[n1] = make_float2(w * z.x, w * z.y);
       }
@@ -316,8 +324,10 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
       for (int n1 = 0; n1 < N1; ++n1) {
         const float w = s_win[n2 * N1 + n1];
         const float2 gy = make_float2(2.f * v[n1].x, -2.f * v[n1].y);
-        if constexpr (DW) {  // the chunk's samples again (they were not kept)
-          const float2 z = centre(buffer_load<InT>(group(a.in, i, s, n1), group_bytes, lane_off));
+        if constexpr (DW) {  // kept, or (complex128) read again
+          float2 z;
+          if constexpr (KEEP_Z) z = zk[n1];
+          else z = centre(buffer_load<InT>(group(a.in, i, s, n1), group_bytes, lane_off));
           const float dw = s_dwin[n2 * N1 + n1];
           dA += (double)dw * ((double)gy.x * z.x + (double)gy.y * z.y);
         }

@@ -409,8 +409,8 @@ def test_deferred_ring_mode_errors(tacaw):
     assert e.value.kind == "UNSUPPORTED"
 
 
-@pytest.mark.parametrize("ring", [0, 256])
-def test_k_space_window_read_in_place(tacaw, ring):
+@pytest.mark.parametrize("ring,tiled", [(0, False), (256, False), (256, True)])
+def test_k_space_window_read_in_place(tacaw, ring, tiled):
     # Sec. II.B crops reciprocal space to a region of interest: a ny x nx window of a
     # wider grid is read in place (pixel rows k_row_stride apart), equal to the
     # reduction of the cropped copy
@@ -422,7 +422,7 @@ def test_k_space_window_read_in_place(tacaw, ring):
     dev = big.cuda()
     view = dev[:, :, y0:y0 + ny, x0:x0 + nx]
     plan = tacaw.Plan(2, ny, nx, 640, 128, 64, masks=torch.from_numpy(masks).cuda(),
-                      k_row_stride=33, ring_frames=ring)
+                      k_row_stride=33, ring_frames=ring, tiled_ring=tiled)
     for f0 in range(0, 640, 64):
         plan.push(view[:, f0:f0 + 64])
     S = plan.finalize().cpu().numpy().reshape(128, -1)
@@ -430,7 +430,7 @@ def test_k_space_window_read_in_place(tacaw, ring):
     plan.close()
     assert rel(S, ref["S"]) < 1e-12 and rel(Dp.cpu().numpy(), ref["Dp"]) < 1e-12
     check({"S": S, "D": D.cpu().numpy(), "Dp": Dp.cpu().numpy()},
-          oracle_all(crop, 128, 64, masks=masks), label=f"k window ring={ring}")
+          oracle_all(crop, 128, 64, masks=masks), label=f"k window ring={ring} tiled={tiled}")
 
 
 def test_k_space_window_adjoint(tacaw):
