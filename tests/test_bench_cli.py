@@ -1,0 +1,31 @@
+"""bench.py contract checks that need no GPU."""
+
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""  # no JSON line for a refused run
+
+
+def test_counter_summaries_name_their_sources_and_commands():
+    # the committed counter summaries carry the hash of the kernel sources they were
+    # taken on; bench.py reports their traffic only while that hash matches
+    sys.path.insert(0, ROOT)
+    import bench
+
+    for name, srcs in [("seg_fft_L512_64probes_counters.json", bench.KERNEL_SOURCES),
+                       ("bwd_kernel_L512_16probes_counters.json", bench.ADJOINT_SOURCES)]:
+        d = json.load(open(os.path.join(ROOT, "profiles", name)))
+        assert len(d["source_sha"]) == 16 and d["commands"]
+        assert d["hbm_bytes_per_launch"] > d["algorithmic_bytes_per_launch"] * 0.99
+        for f in srcs:
+            assert os.path.exists(os.path.join(ROOT, "paper_2607_02236_amd", "csrc", f))
