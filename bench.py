@@ -30,6 +30,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak for the instructions the kernels issue: non-packed FMA on 256 CUs x 64 lanes
+# x 2 flops x 2.4 GHz (the chip's packed-FP32 figure, 157.3 TFLOP/s, needs packed instructions,
+# which this build disables)
+VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+
+
+def fft_flops_per_element(L, H):
+    """Algorithmic flops per input element of the chunk kernel: each element is in L/H
+    chunks; per chunk and point 5 log2 L for the complex FFT (the radix-2 count), 2 for
+    the reference subtraction, 2 for the window, 3 for |X|^2 and 1 for the accumulation."""
+    import math
+
+    return (L / H) * (5.0 * math.log2(L) + 8.0)
 # sources of the chunk kernel and of the adjoint (a counter summary is valid only for these bytes)
 KERNEL_SOURCES = ["seg_fft_kernel.h", "regfft.h", "buffer_io.h", "tacaw_internal.h", "tacaw_fft.hip"]
 ADJOINT_SOURCES = ["tacaw_adjoint.hip", "regfft.h", "buffer_io.h", "tacaw_internal.h"]
@@ -265,6 +278,8 @@ def main():
     value = b_alg / (ms * 1e-3) / 1e9
     k_ms = float(np.mean(kernel_ms))
     achieved = b_alg / (k_ms * 1e-3) / 1e9
+    n_elem = spec.n_probe * spec.n_frames * spec.n_k
+    alu_tf = n_elem * fft_flops_per_element(L, H) / (k_ms * 1e-3) / 1e12
     n_seg = plan.info()["n_segments"]
     m_rows = (2 * n_om + 31) // 32 * 32  # GEMM rows computed (window rows, padded to 32)
     gemm_flops = 3 * 2 * m_rows * 2 * L * n_seg * spec.n_probe * spec.n_k  # executed, 3 products
@@ -298,18 +313,22 @@ def main():
             "seg_len": L, "hop": H, "n_omega": n_om, "exit_wave_bytes": b_alg,
         },
         "roofline": {
-            "bound": "hbm",
+            "bound": "alu",
             "kernel": "seg_fft_kernel",
-            "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "achieved": round(alu_tf, 2),
+            "peak": round(VALU_PEAK_TFLOPS, 1),
+            "unit": "TFLOP/s",
+            "frac": round(alu_tf / VALU_PEAK_TFLOPS, 4),
             "kernel_ms": round(k_ms, 4),
             "traffic": traffic_from_profiles(ksrc),
-            "note": "HBM traffic is ~1.02x the algorithmic bytes; the chunk kernel is bound by "
-                    "non-packed FP32 VALU issue and its latency at two waves per SIMD (about 32 "
-                    "VALU instructions per point and transform, two transforms per element at "
-                    "50% overlap, VALU busy ~67%; peak 39.3 T lane-ops/s), not by HBM",
+            "flops_per_element": round(fft_flops_per_element(L, H), 2),
+            "hbm_achieved_gbs": round(achieved, 2),
+            "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
+            "note": "the chunk kernel is bound by non-packed FP32 VALU issue (about 32 VALU "
+                    "instructions per point and transform, VALU busy ~67% at two waves per "
+                    "SIMD), not by HBM: its HBM traffic is ~1.02x the algorithmic bytes and "
+                    "reaches hbm_frac of 8 TB/s. achieved = algorithmic flops "
+                    "(flops_per_element x elements) / kernel time",
         },
     }
     if gradient:
