@@ -77,7 +77,7 @@ def traffic_from_profiles(kernel_src, name="seg_fft_L512_64probes_counters.json"
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(spec, L, H, n_pix, seed=0, gradient=False):
+def cpu_baseline(spec, L, H, n_pix, seed=0, gradient=False, mean_mode="global"):
     """The FP64 oracle (brute-force DFT) on all probes and frames of a seeded
     subset of pixels (with gradient: the forward and its vector-Jacobian product
     for the detector loss); returns exit-wave GB/s in the metric's unit."""
@@ -98,7 +98,7 @@ def cpu_baseline(spec, L, H, n_pix, seed=0, gradient=False):
         cores = os.cpu_count() or 1
     w = O.window("hann_width" if gradient else "hann", L, 1.0)
     t0 = time.perf_counter()
-    O.tacaw_spectra(psi, L, H, w)
+    O.tacaw_spectra(psi, L, H, w, mean_mode)
     if gradient:
         masks = T.standard_masks(spec.ny, spec.nx, scale=spec.ny / 256).reshape(4, -1)[:, pix]
         gS = np.einsum("jm,jk->mk", T.loss_weights(4, L, seed=4), masks)
@@ -129,6 +129,8 @@ def main():
                          "pushed in pieces of --push-frames frames through the plan's ring; "
                          "gradient: 16 probes x 1024 frames x 128^2 c64, L=H=512, forward + "
                          "adjoint")
+    ap.add_argument("--mean-mode", default="global", choices=["global", "per_segment", "none"],
+                    help="elastic-mean handling (per_segment: each chunk's own mean)")
     ap.add_argument("--push-frames", type=int, default=256)
     ap.add_argument("--ring-frames", type=int, default=0,
                     help="streaming: deferred ring depth per probe (0: chunks run in the push "
@@ -217,7 +219,7 @@ def main():
                       transform=args.form, in_dtype=spec.dtype, time_kernels=True, stream=stream,
                       dt_fs=dt_fs, omega_half=M, ring_frames=args.ring_frames if streaming else 0,
                       tiled_ring=streaming and args.ring_frames > 0 and args.ring_layout == "tiled",
-                      **win)
+                      mean_mode=args.mean_mode, **win)
     R = psi.shape[1]
     pieces = [(f0, min(spec.n_frames, f0 + args.push_frames))
               for f0 in range(0, spec.n_frames, args.push_frames)] if streaming else [(0, spec.n_frames)]
@@ -303,7 +305,8 @@ def main():
         "config": {
             "workload": f"{spec.n_probe} probes x {spec.n_frames} frames x {spec.ny}x{spec.nx} {spec.dtype}, "
                         f"Welch L={L} H={H} " + ("width-r Hann r=1" if gradient else "periodic Hann")
-                        + f", global mean, {masks.shape[0]} detector masks, transform {args.form}"
+                        + f", {args.mean_mode.replace('_', '-')} mean, {masks.shape[0]} detector masks, "
+                          f"transform {args.form}"
                         + (", forward + adjoint (dL/dpsi and dL/dr of sum_j a_j . D_j)" if gradient else "")
                         + (f", pushed in pieces of {args.push_frames} frames" if streaming else "")
                         + (f", deferred ring of {args.ring_frames} frames ({args.ring_layout} layout)"
@@ -360,7 +363,7 @@ def main():
         del psi
         torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(spec, L, H, args.cpu_pixels if not gradient else 8192,
-                                           gradient=gradient)
+                                           gradient=gradient, mean_mode=args.mean_mode)
     plan.close()
     print(json.dumps(out), flush=True)
 

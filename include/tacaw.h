@@ -55,7 +55,11 @@ extern "C" {
 
 /* ---- elastic-mean handling (the mean is removed before the window) ------ */
 #define TACAW_MEAN_GLOBAL 0      /* mean over the frames that enter a chunk (default) */
-#define TACAW_MEAN_PER_SEGMENT 1 /* mean of each chunk (reserved: UNSUPPORTED)        */
+#define TACAW_MEAN_PER_SEGMENT 1 /* unweighted mean of each chunk's own L frames       */
+                                 /* (scipy's detrend='constant'), removed exactly in   */
+                                 /* FP64; needs the FFT transform, a window whose DFT  */
+                                 /* lives on bins 0 and +-1, hop >= L/4 and n_frames   */
+                                 /* < 2^31, else UNSUPPORTED; no tacaw_backward        */
 #define TACAW_MEAN_NONE 2        /* keep the zero-loss peak (the paper's behaviour)   */
 
 /* ---- time transform ------------------------------------------------------ */
@@ -172,7 +176,10 @@ int tacaw_plan_check(const tacaw_plan_desc* desc);
  * chunks still need are copied into a plan-owned ring (last L frames per probe
  * in flight), so a series may arrive in any number of pieces. The result does
  * not depend on how frames or probes are split into pushes (App. B: batch shape
- * does not influence the results).
+ * does not influence the results). A thermalisation period is discarded by
+ * pointing d_frames at the first kept frame, and every s-th stored snapshot
+ * is kept by passing s times the frame pitch as frame_stride (Sec. IV drops
+ * the first picoseconds of each trajectory); no copy is made.
  * Errors: INVALID_ARG (null/misaligned pointer, bad stride), SHAPE (probe range
  * or frame count beyond the plan), STATE (plan finalized, probes at different
  * frame cursors, ring capacity exceeded), OOM, HIP. */

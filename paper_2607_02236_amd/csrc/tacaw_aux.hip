@@ -3,6 +3,8 @@
 // partial reduction, the exact elastic-mean correction, normalisation and the
 // masked detector reduction D_j(m) = sum_k M_j(k) S(m, k) (DetectorSet,
 // Sec. II.B.1 of the paper).
+#include <type_traits>
+
 #include "tacaw_internal.h"
 
 namespace tacaw {
@@ -225,6 +227,7 @@ hipError_t launch_dpart_reduce(const double* dpart, const DetSlots& so, int32_t 
 // mean-subtracted X_s = X'_s - delta W (delta = mu - c):
 //   sum_s |X_s|^2 = sum_s |X'_s|^2 - 2 Re(conj(delta W) sum_s X'_s) + N_s |delta W|^2
 __device__ __forceinline__ double corr_term(const CorrArgs& c, int p, int64_t k, int b) {
+  if (c.pcorr) return c.pcorr[((int64_t)p * kMaxCorr + b) * c.n_k + k];
   const double2 cr = c.cref[(int64_t)p * c.n_k + k];
   double2 delta;
   if (c.mean_global) {
@@ -298,6 +301,112 @@ hipError_t launch_correct_Dp(const CorrArgs& c, const double* masks, int32_t n_d
   const int gx = (int)((c.n_k + 256 * 16 - 1) / (256 * 16));
   hipLaunchKernelGGL(correct_Dp_kernel, dim3(gx > 0 ? gx : 1, c.n_probe), dim3(256), 0, st, c,
                      masks, n_det, Dp);
+  return hipGetLastError();
+}
+
+// ---- per-chunk mean --------------------------------------------------------
+// With its own mean mu_s subtracted, chunk s has at a correction bin b
+//   X_s(b) = A_s(b) - delta_s W(b),  A_s(b) = sum_t w(t) e^{-2 pi i b t / L} y'(s H + t),
+// where y' = psi - c is what the chunk kernel transforms and delta_s = mu_s - c
+// = (1/L) sum_t y'(s H + t). The chunk kernel accumulates |A_s(b)|^2, so the
+// correction is sum_s [-2 Re(conj(delta_s W(b)) A_s(b)) + |delta_s W(b)|^2].
+// One thread per (probe, pixel) walks the push's frames in time order; the V
+// chunks that can hold a frame live in V register slots (chunk s in slot s mod V),
+// a chunk's sums are cleared at its first frame and turned into its correction
+// at its last. Open sums persist in `open` between pushes.
+template <typename InT, int V>
+__global__ void __launch_bounds__(256) pseg_kernel(const PsegArgs a) {
+  constexpr int Q = 1 + kMaxCorr;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (k >= a.n_k || i >= a.n_probes) return;
+  const int p = a.probe0 + i;
+  const InT* src = (const InT*)a.in + (int64_t)i * a.pstride + pix_off(k, a.nx, a.rs);
+  const double2 c = a.cref[(int64_t)p * a.n_k + k];
+  double2* op = a.open + (int64_t)p * V * Q * a.n_k + k;
+  double* cp = a.pcorr + (int64_t)p * kMaxCorr * a.n_k + k;
+  double2 st[V][Q];
+  double cor[kMaxCorr];
+#pragma unroll
+  for (int r = 0; r < V; ++r)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) st[r][q] = op[(int64_t)(r * Q + q) * a.n_k];
+#pragma unroll
+  for (int b = 0; b < kMaxCorr; ++b) cor[b] = cp[(int64_t)b * a.n_k];
+  const int nc = a.n_corr;
+  const double inv_l = 1.0 / (double)a.L;
+  constexpr int U = 4;  // frames loaded ahead
+  for (int64_t n0 = a.f_lo; n0 < a.f_hi; n0 += U) {
+    InT v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (n0 + u < a.f_hi) v[u] = src[(n0 + u - a.base) * a.fstride];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (n0 + u >= a.f_hi) break;
+      const int n = (int)(n0 + u);  // frames below 2^31 (checked by the plan)
+      const double yr = (double)v[u].x - c.x, yi = (double)v[u].y - c.y;
+      // chunks s with s H <= n < s H + L, s < Ns
+      const int s_last = min(a.Ns - 1, n / a.H);
+      const int s_first = n < a.L ? 0 : (n - a.L) / a.H + 1;
+#pragma unroll
+      for (int r = 0; r < V; ++r) {
+        const int s = s_last - (((s_last - r) % V) + V) % V;  // the chunk in slot r
+        if (s < s_first) continue;
+        const int t = n - s * a.H;
+        if (t == 0) {
+#pragma unroll
+          for (int q = 0; q < Q; ++q) st[r][q] = make_double2(0.0, 0.0);
+        }
+        st[r][0].x += yr;
+        st[r][0].y += yi;
+#pragma unroll
+        for (int b = 0; b < kMaxCorr; ++b) {
+          if (b < nc) {
+            const double2 e = a.tw[b * a.L + t];
+            st[r][1 + b].x += e.x * yr - e.y * yi;
+            st[r][1 + b].y += e.x * yi + e.y * yr;
+          }
+        }
+        if (t == a.L - 1) {
+          const double dx = st[r][0].x * inv_l, dy = st[r][0].y * inv_l;
+#pragma unroll
+          for (int b = 0; b < kMaxCorr; ++b) {
+            if (b < nc) {
+              const double2 w = a.wbin[b];
+              const double wx = dx * w.x - dy * w.y, wy = dx * w.y + dy * w.x;
+              cor[b] += -2.0 * (wx * st[r][1 + b].x + wy * st[r][1 + b].y) + (wx * wx + wy * wy);
+            }
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < V; ++r)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) op[(int64_t)(r * Q + q) * a.n_k] = st[r][q];
+#pragma unroll
+  for (int b = 0; b < kMaxCorr; ++b) cp[(int64_t)b * a.n_k] = cor[b];
+}
+
+hipError_t launch_pseg(const PsegArgs& a, int32_t in_dtype, hipStream_t st) {
+  if (a.f_hi <= a.f_lo || a.n_probes < 1) return hipSuccess;
+  if (a.V < 1 || a.V > kMaxPsegOpen) return hipErrorInvalidValue;
+  dim3 g((a.n_k + 255) / 256, a.n_probes);
+  auto go = [&](auto vt) {
+    constexpr int V = decltype(vt)::value;
+    if (in_dtype == 1)
+      hipLaunchKernelGGL((pseg_kernel<double2, V>), g, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((pseg_kernel<float2, V>), g, dim3(256), 0, st, a);
+  };
+  switch (a.V) {
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 3: go(std::integral_constant<int, 3>{}); break;
+    default: go(std::integral_constant<int, 4>{}); break;
+  }
   return hipGetLastError();
 }
 

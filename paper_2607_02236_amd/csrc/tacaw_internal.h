@@ -110,6 +110,7 @@ struct CorrArgs {
   const double2* cref;
   const double2* msum;
   const double2* xs;
+  const double* pcorr;  // [P][3][n_k] per-chunk-mean corrections (null unless that mode)
 };
 // S[i] <- kappa * q[(i / inner) % n_om] * S[i] (q may be null), copied to out when given
 hipError_t launch_finalize_S(double* S, double* out, int64_t n_elem, double kappa, const double* q,
@@ -118,6 +119,23 @@ hipError_t launch_correct_S(const CorrArgs& c, double* S, double* out, double ka
 hipError_t launch_correct_Dp(const CorrArgs& c, const double* masks, int32_t n_det, double* Dp,
                              hipStream_t st);
 hipError_t launch_scale(double* p, int64_t n, double k, hipStream_t st);
+
+// Per-chunk mean (tacaw_aux.hip): streams the frames [f_lo, f_hi) of a push once
+// and keeps, per (probe, pixel) and open chunk, the FP64 sums the exact correction needs.
+constexpr int kMaxPsegOpen = 4;  // chunks that may contain one frame: ceil(L / H)
+struct PsegArgs {
+  const void* in;          // frames of the push; element of absolute frame n at (n - base) * fstride
+  int64_t pstride, fstride, rs;
+  int32_t nx, n_k, probe0, n_probes;
+  int64_t base, f_lo, f_hi;
+  int32_t L, H, Ns, n_corr, V;
+  double2 wbin[kMaxCorr];  // W(bin)
+  const double2* tw;       // [3][L]: w(t) exp(-2 pi i bin t / L)
+  const double2* cref;     // [P][n_k] reference c
+  double2* open;           // [P][V][1 + 3][n_k]: sum_t y', then A(bin) per correction bin
+  double* pcorr;           // [P][3][n_k]
+};
+hipError_t launch_pseg(const PsegArgs& a, int32_t in_dtype, hipStream_t st);
 hipError_t launch_detector(const double* S, const double* masks, int32_t n_det, int32_t L,
                            int32_t n_k, double* D, hipStream_t st);
 

@@ -181,6 +181,10 @@ struct tacaw_plan_s {
   double2* cref = nullptr;  // [P][n_k]
   double2* msum = nullptr;  // [P][n_k]
   double2* xs = nullptr;    // [P][3][n_k]
+  double2* pseg_tw = nullptr;    // per-chunk mean: [3][L] w(t) exp(-2 pi i bin t / L)
+  double2* pseg_open = nullptr;  // per-chunk mean: [P][V][4][n_k] open chunk sums
+  double* pcorr = nullptr;       // per-chunk mean: [P][3][n_k] corrections
+  int pseg_V = 0;                // chunks that can hold one frame, ceil(L / H)
   double* S = nullptr;      // [n_om][n_k]
   double* masks = nullptr;  // [n_det][n_k]
   int32_t* pair_slot = nullptr;  // [n_tiles][n_det]
@@ -422,14 +426,20 @@ int tacaw_plan_check(const tacaw_plan_desc* d) {
     return fail(TACAW_ERR_INVALID_ARG, "HANN_WIDTH needs 0 < window_param <= 4");
   if (d->window == TACAW_WIN_TUKEY && !(d->window_param >= 0.0 && d->window_param <= 1.0))
     return fail(TACAW_ERR_INVALID_ARG, "TUKEY needs 0 <= alpha <= 1");
-  if (d->mean_mode == TACAW_MEAN_PER_SEGMENT)
-    return fail(TACAW_ERR_UNSUPPORTED, "per-segment mean is not implemented");
-  if (d->mean_mode != TACAW_MEAN_GLOBAL && d->mean_mode != TACAW_MEAN_NONE)
+  if (d->mean_mode != TACAW_MEAN_GLOBAL && d->mean_mode != TACAW_MEAN_PER_SEGMENT && d->mean_mode != TACAW_MEAN_NONE)
     return fail(TACAW_ERR_INVALID_ARG, "unknown mean_mode");
   if (d->transform != TACAW_FFT_F32 && !transform_is_gemm(d->transform))
     return fail(TACAW_ERR_INVALID_ARG, "unknown transform");
   if (transform_is_gemm(d->transform) && !seg_gemm_supported(d->seg_len))
     return fail(TACAW_ERR_UNSUPPORTED, "GEMM transform does not support this seg_len");
+  if (d->mean_mode == TACAW_MEAN_PER_SEGMENT) {
+    if (d->transform != TACAW_FFT_F32)
+      return fail(TACAW_ERR_UNSUPPORTED, "per-segment mean needs the FFT transform");
+    if ((d->seg_len + d->hop - 1) / d->hop > kMaxPsegOpen)
+      return fail(TACAW_ERR_UNSUPPORTED, "per-segment mean needs hop >= seg_len / 4");
+    if (d->n_frames >= ((int64_t)1 << 31))
+      return fail(TACAW_ERR_UNSUPPORTED, "per-segment mean needs n_frames < 2^31");
+  }
   if (d->in_dtype != TACAW_C64 && d->in_dtype != TACAW_C128)
     return fail(TACAW_ERR_INVALID_ARG, "unknown in_dtype");
   if (d->probe_reduce != TACAW_PROBE_MEAN && d->probe_reduce != TACAW_PROBE_SUM)
@@ -459,8 +469,9 @@ int tacaw_plan_check(const tacaw_plan_desc* d) {
   }
   const int64_t n_k = (int64_t)d->ny * d->nx;
   const int64_t n_om = d->omega_half > 0 ? 2 * (int64_t)d->omega_half + 1 : d->seg_len;
-  const int64_t need = n_om * n_k * 8 + (int64_t)d->n_probe * n_k * 80 +
-                       (int64_t)d->n_det * n_k * 8;
+  int64_t need = n_om * n_k * 8 + (int64_t)d->n_probe * n_k * 80 + (int64_t)d->n_det * n_k * 8;
+  if (d->mean_mode == TACAW_MEAN_PER_SEGMENT)
+    need += (int64_t)d->n_probe * n_k * (kMaxPsegOpen * (1 + kMaxCorr) * 16 + kMaxCorr * 8);
   if (need > kMaxDeviceBytes) return fail(TACAW_ERR_OOM, "plan accumulators exceed device memory");
   return TACAW_OK;
 }
@@ -538,6 +549,11 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   else
     P->strategy = d->mean_mode == TACAW_MEAN_GLOBAL ? kRefExactMean : kRefZero;
 
+  if (d->mean_mode == TACAW_MEAN_PER_SEGMENT && P->strategy != kRefFirstFrame) {
+    delete P;
+    return fail(TACAW_ERR_UNSUPPORTED,
+                "per-segment mean needs a window whose DFT is confined to bins 0 and +-1");
+  }
   if (P->deferred && P->strategy != kRefFirstFrame) {
     delete P;
     return fail(TACAW_ERR_UNSUPPORTED,
@@ -578,6 +594,12 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   A((void**)&P->msum, np * nk * 16, "mean sums");
   A((void**)&P->xs, np * kMaxCorr * nk * 16, "correction sums");
   A((void**)&P->S, (int64_t)P->n_om * nk * 8, "spectrum accumulator");
+  if (d->mean_mode == TACAW_MEAN_PER_SEGMENT) {
+    P->pseg_V = (P->L + P->H - 1) / P->H;
+    A((void**)&P->pseg_tw, (int64_t)kMaxCorr * P->L * 16, "per-chunk mean twiddles");
+    A((void**)&P->pseg_open, np * P->pseg_V * (1 + kMaxCorr) * nk * 16, "open chunk sums");
+    A((void**)&P->pcorr, np * kMaxCorr * nk * 8, "per-chunk mean corrections");
+  }
   A((void**)&P->scratch, 64, "scratch");
   if (d->temperature_K > 0.0) A((void**)&P->qfac, (int64_t)P->n_om * 8, "quantum factor");
   if (gemm) {
@@ -599,6 +621,15 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   H2D(P->win_t, wt.data(), P->L * 4);
   H2D(P->dwin_t, dwt.data(), P->L * 4);
   H2D(P->tw, twt.data(), P->L * 8);
+  if (P->pseg_tw && rc == TACAW_OK) {
+    std::vector<double2> pt((size_t)kMaxCorr * P->L, make_double2(0.0, 0.0));
+    for (int b = 0; b < P->n_corr; ++b)
+      for (int t = 0; t < P->L; ++t) {
+        const double ang = -kTwoPi * (double)(((int64_t)P->bins[b] * t) % P->L) / P->L;
+        pt[(size_t)b * P->L + t] = make_double2(w[t] * std::cos(ang), w[t] * std::sin(ang));
+      }
+    H2D(P->pseg_tw, pt.data(), (int64_t)pt.size() * 16);
+  }
   if (P->qfac && rc == TACAW_OK) {
     // E_m = h nu_m, nu_m = m / (L dt) (m < L/2) or (m - L) / (L dt); factor x / (1 - e^-x),
     // x = E_m / (k_B T), limit 1 at E = 0
@@ -668,6 +699,11 @@ int tacaw_reset(tacaw_plan_t P) {
   TRY(hip_check(launch_fill_zero(P->cref, np * nk * 16, P->st), "reset"));
   TRY(hip_check(launch_fill_zero(P->msum, np * nk * 16, P->st), "reset"));
   TRY(hip_check(launch_fill_zero(P->xs, np * kMaxCorr * nk * 16, P->st), "reset"));
+  if (P->pcorr) {
+    TRY(hip_check(launch_fill_zero(P->pseg_open, np * P->pseg_V * (1 + kMaxCorr) * nk * 16, P->st),
+                  "reset"));
+    TRY(hip_check(launch_fill_zero(P->pcorr, np * kMaxCorr * nk * 8, P->st), "reset"));
+  }
   // S needs no zero fill: the first chunk launch after a reset writes every element
   if (P->Dp)
     TRY(hip_check(launch_fill_zero(P->Dp, (int64_t)P->d.n_det * np * P->n_om * 8, P->st), "reset"));
@@ -720,6 +756,35 @@ int tacaw_plan_get_info(tacaw_plan_t P, tacaw_plan_info* info) {
 }
 
 void tacaw_destroy(tacaw_plan_t P) { delete P; }
+
+// Per-chunk mean: stream frames [a, min(b, n_used)) of a push through the FP64
+// chunk sums (after the references exist).
+static int run_pseg(tacaw_plan_t P, const void* frames, int64_t pstride, int64_t fstride,
+                    int64_t rs, int32_t probe0, int32_t n_probes, int64_t a, int64_t b) {
+  PsegArgs g{};
+  g.in = frames;
+  g.pstride = pstride;
+  g.fstride = fstride;
+  g.rs = rs;
+  g.nx = P->d.nx;
+  g.n_k = P->n_k;
+  g.probe0 = probe0;
+  g.n_probes = n_probes;
+  g.base = a;
+  g.f_lo = a;
+  g.f_hi = std::min<int64_t>(b, P->n_used);
+  g.L = P->L;
+  g.H = P->H;
+  g.Ns = P->Ns;
+  g.n_corr = P->n_corr;
+  g.V = P->pseg_V;
+  for (int i = 0; i < kMaxCorr; ++i) g.wbin[i] = P->wbin[i];
+  g.tw = P->pseg_tw;
+  g.cref = P->cref;
+  g.open = P->pseg_open;
+  g.pcorr = P->pcorr;
+  return hip_check(launch_pseg(g, P->d.in_dtype, P->st), "per-chunk mean sums");
+}
 
 int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n_probes,
                       int64_t n_frames, int64_t pstride, int64_t fstride) {
@@ -784,6 +849,7 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
                                       P->gscale, P->st),
                     "operand scale pre-pass"));
   }
+  if (P->pcorr) TRY(run_pseg(P, frames, pstride, fstride, P->rs, probe0, n_probes, a, b));
   P->n_timed = 0;
   if (!P->deferred) {
     // 2. every chunk completed by this push, read from the push (and the ring)
@@ -862,6 +928,11 @@ int tacaw_commit_frames(tacaw_plan_t P, int32_t probe0, int32_t n_probes, int64_
                                          n_probes, P->n_k, P->cref, P->st),
                   "reference"));
   }
+  if (P->pcorr) {
+    const int64_t slot0 = probe0 % P->n_slots;
+    TRY(run_pseg(P, (char*)P->ring + ((slot0 * P->D + a % P->D) * P->n_k) * P->esz,
+                 P->D * P->n_k, P->n_k, P->d.nx, probe0, n_probes, a, b));
+  }
   TRY(deferred_finish(P, probe0, n_probes, b));
   advance(P, probe0, n_probes, a, b, true);
   return TACAW_OK;
@@ -883,6 +954,7 @@ static CorrArgs corr_args(tacaw_plan_t P) {
   c.cref = P->cref;
   c.msum = P->msum;
   c.xs = P->xs;
+  c.pcorr = P->pcorr;
   return c;
 }
 
@@ -956,6 +1028,8 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   if (n_probes > 1 && pstride < 1) return fail(TACAW_ERR_INVALID_ARG, "probe_stride must be >= 1");
   if (((int64_t)P->N2 * fstride + P->span) * P->esz > (int64_t)0x7FFFFFFFLL)
     return fail(TACAW_ERR_UNSUPPORTED, "frame_stride too large for 31-bit row-group offsets");
+  if (P->d.mean_mode == TACAW_MEAN_PER_SEGMENT)
+    return fail(TACAW_ERR_UNSUPPORTED, "backward supports the global mean or none");
   if (P->H != P->L && 2 * P->H != P->L)
     return fail(TACAW_ERR_UNSUPPORTED, "backward supports hop = L or hop = L/2");
   if (!is_pow2(P->L)) return fail(TACAW_ERR_UNSUPPORTED, "backward needs a power-of-two seg_len");

@@ -50,7 +50,8 @@ def _ok(**over):
     (dict(ny=0), "INVALID_ARG"),
     (dict(window="hann_width", window_param=0.0), "INVALID_ARG"),
     (dict(window="tukey", window_param=1.5), "INVALID_ARG"),
-    (dict(mean_mode="per_segment"), "UNSUPPORTED"),
+    (dict(mean_mode="per_segment", transform="gemm_bf16x3"), "UNSUPPORTED"),
+    (dict(mean_mode="per_segment", hop=31), "UNSUPPORTED"),  # more than 4 chunks per frame
     (dict(dt_fs=0.0), "INVALID_ARG"),
     (dict(n_det=2), "INVALID_ARG"),
     (dict(max_probes_in_flight=3), "INVALID_ARG"),
@@ -90,6 +91,8 @@ def test_valid_descriptors_pass():
     tacaw.check_desc(**_ok(ring_frames=192))
     tacaw.check_desc(**_ok(ring_frames=192, flags=tacaw.FLAG_TILED_RING))
     tacaw.check_desc(**_ok(k_row_stride=40))
+    tacaw.check_desc(**_ok(mean_mode="per_segment", hop=32))
+    tacaw.check_desc(**_ok(mean_mode="per_segment", ring_frames=192, flags=tacaw.FLAG_TILED_RING))
     tacaw.check_desc(**_ok(seg_len=200, hop=100, n_frames=3200, dt_fs=15.0, omega_half=90))
     tacaw.check_desc(**_ok(omega_half=1, transform="gemm_f16x3", temperature_K=50.0))
 
