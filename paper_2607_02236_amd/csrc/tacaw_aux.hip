@@ -314,9 +314,16 @@ hipError_t launch_correct_Dp(const CorrArgs& c, const double* masks, int32_t n_d
 // chunks that can hold a frame live in V register slots (chunk s in slot s mod V),
 // a chunk's sums are cleared at its first frame and turned into its correction
 // at its last. Open sums persist in `open` between pushes.
-template <typename InT, int V>
+#ifndef TACAW_PSEG_U
+#define TACAW_PSEG_U 16
+#endif
+template <typename InT, int V, bool FAST>
 __global__ void __launch_bounds__(256) pseg_kernel(const PsegArgs a) {
-  constexpr int Q = 1 + kMaxCorr;
+  // Slot state (four double2): the chunk sum of y'; A(0); (P, Q); (R, T) with
+  // P = sum e_r y_r, Q = sum e_i y_i, R = sum e_r y_i, T = sum e_i y_r and
+  // e = w(t) exp(-2 pi i t / L). The window is real, so bins 1 and L - 1 share
+  // them: A(1) = (P - Q, R + T), A(L - 1) = conj(e) y summed = (P + Q, R - T).
+  constexpr int Q = 4;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (k >= a.n_k || i >= a.n_probes) return;
@@ -333,52 +340,145 @@ __global__ void __launch_bounds__(256) pseg_kernel(const PsegArgs a) {
     for (int q = 0; q < Q; ++q) st[r][q] = op[(int64_t)(r * Q + q) * a.n_k];
 #pragma unroll
   for (int b = 0; b < kMaxCorr; ++b) cor[b] = cp[(int64_t)b * a.n_k];
-  const int nc = a.n_corr;
+  const bool three = a.n_corr == 3;
   const double inv_l = 1.0 / (double)a.L;
-  constexpr int U = 4;  // frames loaded ahead
+  const double* w0 = (const double*)a.tw;  // w(t) = Re tw[0][t], stride 2
+  const double2* e1 = a.tw + a.L;         // w(t) exp(-2 pi i t / L)
+  constexpr int U = TACAW_PSEG_U;         // frames in flight per thread
+  // add the chunk's correction from its finished sums
+  auto close = [&](const double2 (&z)[Q]) {
+    const double dx = z[0].x * inv_l, dy = z[0].y * inv_l;
+    double2 A[kMaxCorr];
+    A[0] = z[1];
+    A[1] = make_double2(z[2].x - z[2].y, z[3].x + z[3].y);
+    A[2] = make_double2(z[2].x + z[2].y, z[3].x - z[3].y);
+#pragma unroll
+    for (int b = 0; b < kMaxCorr; ++b) {
+      if (b == 0 || three) {
+        const double2 wb = a.wbin[b];
+        const double wx = dx * wb.x - dy * wb.y, wy = dx * wb.y + dy * wb.x;
+        cor[b] += -2.0 * (wx * A[b].x + wy * A[b].y) + (wx * wx + wy * wy);
+      }
+    }
+  };
+  if constexpr (FAST) {
+    // H divides L (FAST is chosen when L = V H): frame n = j H + u lies in chunks j - q, q = 0..V-1, at
+    // t = q H + u, so inside a hop block every frame updates the same V sums
+    // with no bookkeeping; chunk j starts at u = 0 and chunk j - V + 1 ends
+    // after u = H - 1. Register sq[q] holds chunk j - q (HBM slot (j - q) mod V);
+    // sums of chunks that do not exist (j - q < 0) are never closed.
+    double2 sq[V][Q];
+    const int jb = (int)(a.f_lo / a.H);
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const int slot = ((jb - q) % V + V) % V;
+#pragma unroll
+      for (int z = 0; z < Q; ++z) sq[q][z] = st[0][z];
+#pragma unroll
+      for (int r = 1; r < V; ++r)
+        if (slot == r)
+#pragma unroll
+          for (int z = 0; z < Q; ++z) sq[q][z] = st[r][z];
+    }
+    int64_t n = a.f_lo;
+    while (n < a.f_hi) {
+      const int j = (int)(n / a.H);
+      const int u0 = (int)(n - (int64_t)j * a.H);
+      const int u1 = (int)min<int64_t>(a.H, u0 + (a.f_hi - n));
+      if (u0 == 0) {
+#pragma unroll
+        for (int z = 0; z < Q; ++z) sq[0][z] = make_double2(0.0, 0.0);
+      }
+      const InT* fp = src + (n - a.base) * a.fstride;
+      for (int u = u0; u < u1; u += U) {
+        InT v[U];
+#pragma unroll
+        for (int x = 0; x < U; ++x)
+          if (u + x < u1) v[x] = fp[(int64_t)(u + x - u0) * a.fstride];
+#pragma unroll
+        for (int x = 0; x < U; ++x) {
+          if (u + x >= u1) continue;
+          const double yr = (double)v[x].x - c.x, yi = (double)v[x].y - c.y;
+#pragma unroll
+          for (int q = 0; q < V; ++q) {
+            const int t = q * a.H + u + x;
+            const double w = w0[2 * t];
+            sq[q][0].x += yr;
+            sq[q][0].y += yi;
+            sq[q][1].x += w * yr;
+            sq[q][1].y += w * yi;
+            if (three) {
+              const double2 e = e1[t];
+              sq[q][2].x += e.x * yr;
+              sq[q][2].y += e.y * yi;
+              sq[q][3].x += e.x * yi;
+              sq[q][3].y += e.y * yr;
+            }
+          }
+        }
+      }
+      n += u1 - u0;
+      if (u1 == a.H) {  // hop block j is complete
+        const int s_end = j - (V - 1);
+        if (s_end >= 0 && s_end < a.Ns) close(sq[V - 1]);
+#pragma unroll
+        for (int q = V - 1; q > 0; --q)
+#pragma unroll
+          for (int z = 0; z < Q; ++z) sq[q][z] = sq[q - 1][z];
+      }
+    }
+    // back to HBM slots: register q now holds chunk je - q
+    const int je = (int)(a.f_hi / a.H);
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const int slot = ((je - q) % V + V) % V;
+#pragma unroll
+      for (int z = 0; z < Q; ++z) op[(int64_t)(slot * Q + z) * a.n_k] = sq[q][z];
+    }
+#pragma unroll
+    for (int b = 0; b < kMaxCorr; ++b) cp[(int64_t)b * a.n_k] = cor[b];
+    return;
+  } else {
   for (int64_t n0 = a.f_lo; n0 < a.f_hi; n0 += U) {
     InT v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (n0 + u < a.f_hi) v[u] = src[(n0 + u - a.base) * a.fstride];
+    // uniform bookkeeping: frame n = n0 + u lies after chunk start sl * H + rem
+    int sl = (int)(n0 / a.H);
+    int rem = (int)(n0 - (int64_t)sl * a.H);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (n0 + u >= a.f_hi) break;
       const int n = (int)(n0 + u);  // frames below 2^31 (checked by the plan)
       const double yr = (double)v[u].x - c.x, yi = (double)v[u].y - c.y;
-      // chunks s with s H <= n < s H + L, s < Ns
-      const int s_last = min(a.Ns - 1, n / a.H);
-      const int s_first = n < a.L ? 0 : (n - a.L) / a.H + 1;
+      const int smax = min(a.Ns - 1, sl);  // the latest chunk that has started
 #pragma unroll
       for (int r = 0; r < V; ++r) {
-        const int s = s_last - (((s_last - r) % V) + V) % V;  // the chunk in slot r
-        if (s < s_first) continue;
+        const int s = smax - (((smax - r) % V) + V) % V;  // the chunk in slot r
         const int t = n - s * a.H;
+        if (s < 0 || t >= a.L) continue;  // no chunk of slot r holds frame n
         if (t == 0) {
 #pragma unroll
           for (int q = 0; q < Q; ++q) st[r][q] = make_double2(0.0, 0.0);
         }
+        const double w = w0[2 * t];
         st[r][0].x += yr;
         st[r][0].y += yi;
-#pragma unroll
-        for (int b = 0; b < kMaxCorr; ++b) {
-          if (b < nc) {
-            const double2 e = a.tw[b * a.L + t];
-            st[r][1 + b].x += e.x * yr - e.y * yi;
-            st[r][1 + b].y += e.x * yi + e.y * yr;
-          }
+        st[r][1].x += w * yr;
+        st[r][1].y += w * yi;
+        if (three) {
+          const double2 e = e1[t];
+          st[r][2].x += e.x * yr;
+          st[r][2].y += e.y * yi;
+          st[r][3].x += e.x * yi;
+          st[r][3].y += e.y * yr;
         }
-        if (t == a.L - 1) {
-          const double dx = st[r][0].x * inv_l, dy = st[r][0].y * inv_l;
-#pragma unroll
-          for (int b = 0; b < kMaxCorr; ++b) {
-            if (b < nc) {
-              const double2 w = a.wbin[b];
-              const double wx = dx * w.x - dy * w.y, wy = dx * w.y + dy * w.x;
-              cor[b] += -2.0 * (wx * st[r][1 + b].x + wy * st[r][1 + b].y) + (wx * wx + wy * wy);
-            }
-          }
-        }
+        if (t == a.L - 1) close(st[r]);
+      }
+      if (++rem == a.H) {
+        rem = 0;
+        ++sl;
       }
     }
   }
@@ -388,18 +488,27 @@ __global__ void __launch_bounds__(256) pseg_kernel(const PsegArgs a) {
     for (int q = 0; q < Q; ++q) op[(int64_t)(r * Q + q) * a.n_k] = st[r][q];
 #pragma unroll
   for (int b = 0; b < kMaxCorr; ++b) cp[(int64_t)b * a.n_k] = cor[b];
+  }
 }
 
 hipError_t launch_pseg(const PsegArgs& a, int32_t in_dtype, hipStream_t st) {
   if (a.f_hi <= a.f_lo || a.n_probes < 1) return hipSuccess;
   if (a.V < 1 || a.V > kMaxPsegOpen) return hipErrorInvalidValue;
   dim3 g((a.n_k + 255) / 256, a.n_probes);
+  const bool fast = a.L == a.V * a.H;
   auto go = [&](auto vt) {
     constexpr int V = decltype(vt)::value;
-    if (in_dtype == 1)
-      hipLaunchKernelGGL((pseg_kernel<double2, V>), g, dim3(256), 0, st, a);
-    else
-      hipLaunchKernelGGL((pseg_kernel<float2, V>), g, dim3(256), 0, st, a);
+    if (in_dtype == 1) {
+      if (fast)
+        hipLaunchKernelGGL((pseg_kernel<double2, V, true>), g, dim3(256), 0, st, a);
+      else
+        hipLaunchKernelGGL((pseg_kernel<double2, V, false>), g, dim3(256), 0, st, a);
+    } else {
+      if (fast)
+        hipLaunchKernelGGL((pseg_kernel<float2, V, true>), g, dim3(256), 0, st, a);
+      else
+        hipLaunchKernelGGL((pseg_kernel<float2, V, false>), g, dim3(256), 0, st, a);
+    }
   };
   switch (a.V) {
     case 1: go(std::integral_constant<int, 1>{}); break;

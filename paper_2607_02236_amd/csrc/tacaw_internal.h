@@ -130,9 +130,9 @@ struct PsegArgs {
   int64_t base, f_lo, f_hi;
   int32_t L, H, Ns, n_corr, V;
   double2 wbin[kMaxCorr];  // W(bin)
-  const double2* tw;       // [3][L]: w(t) exp(-2 pi i bin t / L)
+  const double2* tw;       // [3][L]: w(t) exp(-2 pi i bin t / L), bins 0, 1, L - 1 (rows 0, 1 read)
   const double2* cref;     // [P][n_k] reference c
-  double2* open;           // [P][V][1 + 3][n_k]: sum_t y', then A(bin) per correction bin
+  double2* open;           // [P][V][4][n_k]: open chunk sums (layout in pseg_kernel)
   double* pcorr;           // [P][3][n_k]
 };
 hipError_t launch_pseg(const PsegArgs& a, int32_t in_dtype, hipStream_t st);
