@@ -276,6 +276,19 @@ def main():
     ms = e0.elapsed_time(e1) / args.steps
     log(f"timed {args.steps} steps: {ms:.3f} ms/step; chunk kernel {np.mean(kernel_ms):.3f} ms")
 
+    # measured HBM read ceiling: the read probe over the resident input (untimed region)
+    ceil_ms = []
+    for _ in range(5):
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        tacaw.read_probe(psi, stream=stream)
+        c1.record(stream)
+        c1.synchronize()
+        ceil_ms.append(c0.elapsed_time(c1))
+    read_ceiling = psi.numel() * psi.element_size() / (float(np.median(ceil_ms)) * 1e-3) / 1e9
+    log(f"read probe over {psi.numel() * psi.element_size() / 1e9:.1f} GB: {read_ceiling:.0f} GB/s")
+
     b_alg = spec.nbytes  # each unique exit-wave value once
     value = b_alg / (ms * 1e-3) / 1e9
     k_ms = float(np.mean(kernel_ms))
@@ -358,6 +371,8 @@ def main():
             "note": "executed MFMA flops (3 split products of the real GEMM with "
                     f"{m_rows} rows x {2 * L} per chunk); useful flops are one third",
         }
+    out["roofline"]["read_ceiling_gbs"] = round(read_ceiling, 1)
+    out["roofline"]["value_frac_of_read_ceiling"] = round(value / read_ceiling, 4)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         del psi

@@ -266,6 +266,17 @@ const char* tacaw_last_error(void);
 /* Library version string. */
 const char* tacaw_version(void);
 
+/* Measured HBM read ceiling (measurement support, not a step of the method):
+ * reads every byte of the device buffer d_buf once with 16-byte vector loads
+ * and stores the wrapping (mod 2^64) sum of its little-endian 64-bit words in
+ * the device scalar *d_sum, so the reads cannot be elided and the result is
+ * checkable. Timing the call (HIP events on hip_stream) over a buffer far larger
+ * than the caches gives the read bandwidth the chunk transform's exit-wave
+ * rate is compared with, next to the datasheet HBM peak. n_bytes must be a
+ * positive multiple of 16 and d_buf 16-byte aligned; stream-ordered, nothing
+ * is allocated. Errors: INVALID_ARG, HIP. */
+int tacaw_read_probe(const void* d_buf, int64_t n_bytes, void* hip_stream, uint64_t* d_sum);
+
 #ifdef __cplusplus
 }
 #endif

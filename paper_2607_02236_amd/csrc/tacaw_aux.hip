@@ -519,6 +519,50 @@ hipError_t launch_pseg(const PsegArgs& a, int32_t in_dtype, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---- HBM read ceiling ------------------------------------------------------
+// Grid-stride read of 16-byte words, TACAW_READ_U independent loads per thread
+// and trip, summed as 64-bit words (wrapping); one atomic per block.
+#ifndef TACAW_READ_U
+#define TACAW_READ_U 16
+#endif
+__global__ void __launch_bounds__(256) read_probe_kernel(const uint4* __restrict__ p, int64_t n16,
+                                                         unsigned long long* sum) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long acc = 0;
+  auto add = [&](const uint4 v) {
+    acc += ((unsigned long long)v.y << 32 | v.x) + ((unsigned long long)v.w << 32 | v.z);
+  };
+  constexpr int U = TACAW_READ_U;
+  for (; i + (U - 1) * stride < n16; i += U * stride) {
+    uint4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = p[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < U; ++u) add(v[u]);
+  }
+  for (; i < n16; i += stride) add(p[i]);
+  __shared__ unsigned long long red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(sum, red[0]);
+}
+
+hipError_t launch_read_probe(const void* p, int64_t bytes, uint64_t* sum, hipStream_t st) {
+  hipError_t e = launch_fill_zero(sum, 8, st);
+  if (e != hipSuccess) return e;
+  const int64_t n16 = bytes / 16;
+  const int64_t want = (n16 + TACAW_READ_U * 256 - 1) / (TACAW_READ_U * 256);
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, 256 * 32));
+  hipLaunchKernelGGL(read_probe_kernel, dim3(blocks), dim3(256), 0, st, (const uint4*)p, n16,
+                     (unsigned long long*)sum);
+  return hipGetLastError();
+}
+
 // S[i] <- kappa q(r) S[i], row r = (i / inner) % n_om (q null: factor 1); copy to out if given
 __global__ void scale_copy_kernel(double* S, double* out, int64_t n, double kappa, const double* q,
                                   int64_t inner, int32_t n_om) {

@@ -402,6 +402,16 @@ extern "C" {
 const char* tacaw_last_error(void) { return g_err.c_str(); }
 const char* tacaw_version(void) { return "tacaw-mi355x 0.1"; }
 
+int tacaw_read_probe(const void* d_buf, int64_t n_bytes, void* hip_stream, uint64_t* d_sum) {
+  g_err.clear();
+  if (!d_buf || !d_sum) return fail(TACAW_ERR_INVALID_ARG, "buffer and sum must not be NULL");
+  if (n_bytes <= 0 || n_bytes % 16 != 0)
+    return fail(TACAW_ERR_INVALID_ARG, "n_bytes must be a positive multiple of 16");
+  if (((uintptr_t)d_buf) % 16 != 0 || ((uintptr_t)d_sum) % 8 != 0)
+    return fail(TACAW_ERR_INVALID_ARG, "buffer must be 16-byte and sum 8-byte aligned");
+  return hip_check(launch_read_probe(d_buf, n_bytes, d_sum, (hipStream_t)hip_stream), "read probe");
+}
+
 int tacaw_plan_check(const tacaw_plan_desc* d) {
   g_err.clear();
   if (!d) return fail(TACAW_ERR_INVALID_ARG, "desc is NULL");

@@ -79,6 +79,7 @@ def _load():
         "tacaw_destroy": (None, [P]),
         "tacaw_last_error": (C.c_char_p, []),
         "tacaw_version": (C.c_char_p, []),
+        "tacaw_read_probe": (C.c_int, [P, C.c_int64, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -91,7 +92,8 @@ lib = _load()
 EXPORTED = ("tacaw_plan", "tacaw_plan_check", "tacaw_push_frames", "tacaw_ingest_frames",
             "tacaw_commit_frames", "tacaw_finalize",
             "tacaw_detector_spectra", "tacaw_backward", "tacaw_reset", "tacaw_set_stream",
-            "tacaw_plan_get_info", "tacaw_destroy", "tacaw_last_error", "tacaw_version")
+            "tacaw_plan_get_info", "tacaw_destroy", "tacaw_last_error", "tacaw_version",
+            "tacaw_read_probe")
 
 
 def _check(rc):
@@ -336,3 +338,16 @@ def spectra(frames, seg_len, hop=None, masks=None, per_probe=False, **kw):
         D = plan.detector_spectra(per_probe=per_probe)
         torch.cuda.current_stream().synchronize()
         return (S, *D) if per_probe else (S, D)
+
+
+def read_probe(buf: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Read every byte of a contiguous CUDA tensor once (the HBM read-ceiling probe);
+    returns a 1-element int64 CUDA tensor with the wrapping sum of its 64-bit words."""
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("read_probe needs a contiguous CUDA tensor")
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=buf.device)
+    s, sptr = _stream_ptr(stream)
+    _check(lib.tacaw_read_probe(C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(), sptr,
+                                C.c_void_p(out.data_ptr())))
+    return out

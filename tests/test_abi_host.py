@@ -108,6 +108,7 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.tacaw_finalize(None, None) == -1
     assert lib.tacaw_detector_spectra(None, None, 0, None, None) == -1
     assert lib.tacaw_reset(None) == -1
+    assert lib.tacaw_read_probe(None, 16, None, None) == -1
     lib.tacaw_destroy(None)
 
 
