@@ -62,9 +62,9 @@ def source_sha(paths):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_src, name="seg_fft_L512_64probes_counters.json"):
+def traffic_from_profiles(kernel_src, config, name="seg_fft_L512_64probes_counters.json"):
     """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel source; else None."""
+    on the current kernel source and on this run's workload; else None."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -72,7 +72,7 @@ def traffic_from_profiles(kernel_src, name="seg_fft_L512_64probes_counters.json"
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("source_sha") != source_sha(kernel_src):
+    if d.get("source_sha") != source_sha(kernel_src) or d.get("config") != config:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -299,6 +299,10 @@ def main():
     m_rows = (2 * n_om + 31) // 32 * 32  # GEMM rows computed (window rows, padded to 32)
     gemm_flops = 3 * 2 * m_rows * 2 * L * n_seg * spec.n_probe * spec.n_k  # executed, 3 products
     csrc = os.path.join(ROOT, "paper_2607_02236_amd", "csrc")
+    # what the committed counter summaries must have measured for their traffic to apply
+    run_cfg = dict(probes=spec.n_probe, frames=spec.n_frames, ny=spec.ny, nx=spec.nx, seg_len=L,
+                   hop=H, dtype=spec.dtype, form=args.form, mean_mode=args.mean_mode,
+                   streaming=bool(streaming), gradient=bool(gradient), omega_half=int(M))
     ksrc = [os.path.join(csrc, f) for f in KERNEL_SOURCES] \
         if args.form == "fft" else [os.path.join(csrc, "tacaw_gemm.hip")]
     out = {
@@ -336,7 +340,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(alu_tf / VALU_PEAK_TFLOPS, 4),
             "kernel_ms": round(k_ms, 4),
-            "traffic": traffic_from_profiles(ksrc),
+            "traffic": traffic_from_profiles(ksrc, run_cfg),
             "flops_per_element": round(fft_flops_per_element(L, H), 2),
             "hbm_achieved_gbs": round(achieved, 2),
             "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -354,7 +358,7 @@ def main():
             "bound": "hbm", "kernel": "bwd_kernel", "achieved": round(ach_b, 2),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach_b / HBM_PEAK_GBS, 4),
             "kernel_ms": round(t_b, 4),
-            "traffic": traffic_from_profiles([os.path.join(csrc, f) for f in ADJOINT_SOURCES],
+            "traffic": traffic_from_profiles([os.path.join(csrc, f) for f in ADJOINT_SOURCES], run_cfg,
                                              "bwd_kernel_L512_16probes_counters.json"),
             "forward_chunk_kernel_ms": round(k_ms, 4),
             "note": "adjoint launch (bwd_kernel and the window-parameter reduction): reads "
