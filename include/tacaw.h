@@ -59,7 +59,7 @@ extern "C" {
                                  /* (scipy's detrend='constant'), removed exactly in   */
                                  /* FP64; needs the FFT transform, a window whose DFT  */
                                  /* lives on bins 0 and +-1, hop >= L/4 and n_frames   */
-                                 /* < 2^31, else UNSUPPORTED; no tacaw_backward        */
+                                 /* < 2^31, else UNSUPPORTED                           */
 #define TACAW_MEAN_NONE 2        /* keep the zero-loss peak (the paper's behaviour)   */
 
 /* ---- time transform ------------------------------------------------------ */
@@ -240,7 +240,8 @@ int tacaw_detector_spectra(tacaw_plan_t plan, const double* d_masks_or_null, int
  * dtype and strides as d_frames, d/dRe + i d/dIm convention; it is fully
  * written for frames < frames_used and left untouched beyond. d_grad_wparam:
  * device float64 scalar that receives (+=) dLoss/d(window_param) for
- * HANN_WIDTH plans (may be NULL). Mean modes GLOBAL and NONE.
+ * HANN_WIDTH plans (may be NULL). All mean modes; with PER_SEGMENT each
+ * chunk's mean is taken from the forward pass too.
  * Errors: STATE (not finalized), INVALID_ARG, UNSUPPORTED, HIP. */
 int tacaw_backward(tacaw_plan_t plan, const void* d_frames, int32_t probe0, int32_t n_probes,
                    int64_t probe_stride, int64_t frame_stride, const double* d_gS,

@@ -72,7 +72,11 @@ __device__ __forceinline__ float2 rot_g(float2 x, int e) {
 // centred samples again after both transforms; they are re-read then rather
 // than kept in registers through the transforms.
 // MT: mean term. 0: none (no mean subtracted); 1: accumulate its sum for the
-// separate pass; 2: from the forward pass's bin sums, subtracted at the stores.
+// separate pass; 2: from the forward pass's bin sums, subtracted at the stores;
+// 3: per-chunk means (chunk s subtracts its own mean mu_s, from the forward
+// pass): the frames of chunk s get 2 w g_s - M_s / L with
+// M_s = 2 sum_b G(b) conj(W(b)) X_s(b) over the bins where W != 0, posted by the
+// bin-role threads that hold those bins.
 template <int L, typename InT, bool DW, int MT>
 __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
     bwd_kernel(const BwdArgs a) {
@@ -93,6 +97,7 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
   __shared__ float s_dwin[DW ? L : 1];
   __shared__ double red[2 * NT];
   __shared__ float s_mk[kMaxDet * W];  // detector masks of the tile's pixels
+  __shared__ double2 s_mt[MT == 3 ? kMaxCorr * W : 1];  // MT 3: M_s terms per bin and pixel
   float2* const xa = xbuf2;
   float2* const xi = xbuf2 + TILE;
 
@@ -179,7 +184,7 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
     }
     // mu = c + delta, delta = (sum over the used frames of psi - c) / N_used
     double2 mu = make_double2(0.0, 0.0), delta = make_double2(0.0, 0.0);
-    if constexpr (MT != 0) {
+    if constexpr (MT == 1 || MT == 2) {
       const double2 cr = a.cref[(int64_t)p * n_k + kc];
       const double2 ms = a.msum[(int64_t)p * n_k + kc];
       delta = make_double2(ms.x * a.inv_nused, ms.y * a.inv_nused);
@@ -213,6 +218,8 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
       auto centre = [&](const InT& x) -> float2 {
         return make_float2((float)((double)x.x - mu.x), (float)((double)x.y - mu.y));
       };
+      // MT 3: this chunk's mean (read here rather than carried through the transforms)
+      if constexpr (MT == 3) mu = a.cmean[((int64_t)p * a.n_seg + s) * n_k + kc];
       float2 v[N1];
       // DW (complex64): the centred samples stay in registers for the r-derivative
       // (re-reading them at the end of the chunk missed the L2 and doubled the reads)
@@ -269,6 +276,19 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
         }
         dft_inplace<N1>(X);
       }
+      if constexpr (MT == 3) {  // this thread's share of M_s (bins 0, 1, L - 1)
+#pragma unroll
+        for (int t = 0; t < N1; ++t) {
+          const int m = bin(t);
+          const int b = m == 0 ? 0 : (m == 1 ? 1 : (m == L - 1 ? 2 : -1));
+          if (b >= 0 && b < a.n_corr) {
+            const double g = 2.0 * (double)Gt[t];
+            const double2 wb = a.wbin[b];
+            const double xx = X[t].x, xy = X[t].y;
+            s_mt[b * W + px] = make_double2(g * (wb.x * xx + wb.y * xy), g * (wb.x * xy - wb.y * xx));
+          }
+        }
+      }
       // ---- weight by G: loss value; conj(Z) = conj(G X)
 #pragma unroll
       for (int t = 0; t < N1; ++t) {
@@ -319,6 +339,16 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
 #pragma unroll
       for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], s_tw[n2 * N1 + k1]);
       dft_inplace<N1>(v);  // v[n1] = conj(g_y(N2 n1 + n2)) / 2
+      float2 msub = make_float2(0.f, 0.f);  // MT 3: M_s / L
+      if constexpr (MT == 3) {
+        double2 M = make_double2(0.0, 0.0);
+        for (int b = 0; b < a.n_corr; ++b) {
+          const double2 e = s_mt[b * W + px];
+          M.x += e.x;
+          M.y += e.y;
+        }
+        msub = make_float2((float)(M.x / L), (float)(M.y / L));
+      }
       // g_z = w g_y; r-derivative term; mean-term sum; overlap carry and stores
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) {
@@ -331,7 +361,7 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
           const float dw = s_dwin[n2 * N1 + n1];
           dA += (double)dw * ((double)gy.x * z.x + (double)gy.y * z.y);
         }
-        v[n1] = make_float2(w * gy.x, w * gy.y);
+        v[n1] = make_float2(w * gy.x - msub.x, w * gy.y - msub.y);
         if constexpr (MT == 1) {
           gsum.x += (double)v[n1].x;
           gsum.y += (double)v[n1].y;
@@ -443,7 +473,7 @@ template <int L>
 static hipError_t launch_bl(int in_dtype, const BwdArgs& a, int n_tiles, hipStream_t st) {
   constexpr int NT = BwdShape<L>::W * (L / BwdShape<L>::N1);
   const bool dw = a.dwin_t != nullptr;
-  const int mt = a.mean_global ? (a.n_corr > 0 ? 2 : 1) : 0;
+  const int mt = a.per_chunk ? 3 : (a.mean_global ? (a.n_corr > 0 ? 2 : 1) : 0);
   auto go = [&](auto in_t, auto dw_c, auto mt_c) {
     hipLaunchKernelGGL((bwd_kernel<L, decltype(in_t), decltype(dw_c)::value, decltype(mt_c)::value>),
                        dim3(n_tiles), dim3(NT), 0, st, a);
@@ -453,8 +483,10 @@ static hipError_t launch_bl(int in_dtype, const BwdArgs& a, int n_tiles, hipStre
   using M0 = std::integral_constant<int, 0>;
   using M1 = std::integral_constant<int, 1>;
   using M2 = std::integral_constant<int, 2>;
+  using M3 = std::integral_constant<int, 3>;
   auto by_mt = [&](auto in_t, auto dw_c) {
-    if (mt == 2) go(in_t, dw_c, M2{});
+    if (mt == 3) go(in_t, dw_c, M3{});
+    else if (mt == 2) go(in_t, dw_c, M2{});
     else if (mt == 1) go(in_t, dw_c, M1{});
     else go(in_t, dw_c, M0{});
   };

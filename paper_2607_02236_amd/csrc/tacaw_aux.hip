@@ -345,9 +345,10 @@ __global__ void __launch_bounds__(256) pseg_kernel(const PsegArgs a) {
   const double* w0 = (const double*)a.tw;  // w(t) = Re tw[0][t], stride 2
   const double2* e1 = a.tw + a.L;         // w(t) exp(-2 pi i t / L)
   constexpr int U = TACAW_PSEG_U;         // frames in flight per thread
-  // add the chunk's correction from its finished sums
-  auto close = [&](const double2 (&z)[Q]) {
+  // add chunk s's correction from its finished sums and keep its mean
+  auto close = [&](const double2 (&z)[Q], int s) {
     const double dx = z[0].x * inv_l, dy = z[0].y * inv_l;
+    a.cmean[((int64_t)p * a.Ns + s) * a.n_k + k] = make_double2(c.x + dx, c.y + dy);
     double2 A[kMaxCorr];
     A[0] = z[1];
     A[1] = make_double2(z[2].x - z[2].y, z[3].x + z[3].y);
@@ -420,7 +421,7 @@ __global__ void __launch_bounds__(256) pseg_kernel(const PsegArgs a) {
       n += u1 - u0;
       if (u1 == a.H) {  // hop block j is complete
         const int s_end = j - (V - 1);
-        if (s_end >= 0 && s_end < a.Ns) close(sq[V - 1]);
+        if (s_end >= 0 && s_end < a.Ns) close(sq[V - 1], s_end);
 #pragma unroll
         for (int q = V - 1; q > 0; --q)
 #pragma unroll
@@ -474,7 +475,7 @@ __global__ void __launch_bounds__(256) pseg_kernel(const PsegArgs a) {
           st[r][3].x += e.x * yi;
           st[r][3].y += e.y * yr;
         }
-        if (t == a.L - 1) close(st[r]);
+        if (t == a.L - 1) close(st[r], s);
       }
       if (++rem == a.H) {
         rem = 0;

@@ -135,6 +135,7 @@ struct PsegArgs {
   const double2* cref;     // [P][n_k] reference c
   double2* open;           // [P][V][4][n_k]: open chunk sums (layout in pseg_kernel)
   double* pcorr;           // [P][3][n_k]
+  double2* cmean;          // [P][Ns][n_k]: each chunk's FP64 mean c + sum_t y' / L
 };
 hipError_t launch_pseg(const PsegArgs& a, int32_t in_dtype, hipStream_t st);
 hipError_t launch_detector(const double* S, const double* masks, int32_t n_det, int32_t L,
@@ -159,6 +160,8 @@ struct BwdArgs {
   int32_t n_k, probe0, n_probes, n_probe_total, n_seg, hop, n_det;
   int32_t n_om, roi_half;  // output rows and energy window (bin m -> row (m + M) mod L)
   int32_t mean_global;
+  int32_t per_chunk;       // per-chunk mean: chunk s subtracts cmean[p][s][k]
+  const double2* cmean;    // [n_probe][n_seg][n_k] chunk means from the forward pass
   double inv_nused;
   int64_t n_used;
   const float* win_t;      // [N2][N1]

@@ -184,6 +184,7 @@ struct tacaw_plan_s {
   double2* pseg_tw = nullptr;    // per-chunk mean: [3][L] w(t) exp(-2 pi i bin t / L)
   double2* pseg_open = nullptr;  // per-chunk mean: [P][V][4][n_k] open chunk sums
   double* pcorr = nullptr;       // per-chunk mean: [P][3][n_k] corrections
+  double2* cmean = nullptr;      // per-chunk mean: [P][Ns][n_k] chunk means (for the adjoint)
   int pseg_V = 0;                // chunks that can hold one frame, ceil(L / H)
   double* S = nullptr;      // [n_om][n_k]
   double* masks = nullptr;  // [n_det][n_k]
@@ -481,7 +482,8 @@ int tacaw_plan_check(const tacaw_plan_desc* d) {
   const int64_t n_om = d->omega_half > 0 ? 2 * (int64_t)d->omega_half + 1 : d->seg_len;
   int64_t need = n_om * n_k * 8 + (int64_t)d->n_probe * n_k * 80 + (int64_t)d->n_det * n_k * 8;
   if (d->mean_mode == TACAW_MEAN_PER_SEGMENT)
-    need += (int64_t)d->n_probe * n_k * (kMaxPsegOpen * (1 + kMaxCorr) * 16 + kMaxCorr * 8);
+    need += (int64_t)d->n_probe * n_k * (kMaxPsegOpen * (1 + kMaxCorr) * 16 + kMaxCorr * 8 +
+                                         seg_count(d->n_frames, d->seg_len, d->hop) * 16);
   if (need > kMaxDeviceBytes) return fail(TACAW_ERR_OOM, "plan accumulators exceed device memory");
   return TACAW_OK;
 }
@@ -609,6 +611,7 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
     A((void**)&P->pseg_tw, (int64_t)kMaxCorr * P->L * 16, "per-chunk mean twiddles");
     A((void**)&P->pseg_open, np * P->pseg_V * (1 + kMaxCorr) * nk * 16, "open chunk sums");
     A((void**)&P->pcorr, np * kMaxCorr * nk * 8, "per-chunk mean corrections");
+    A((void**)&P->cmean, np * P->Ns * nk * 16, "chunk means");
   }
   A((void**)&P->scratch, 64, "scratch");
   if (d->temperature_K > 0.0) A((void**)&P->qfac, (int64_t)P->n_om * 8, "quantum factor");
@@ -793,6 +796,7 @@ static int run_pseg(tacaw_plan_t P, const void* frames, int64_t pstride, int64_t
   g.cref = P->cref;
   g.open = P->pseg_open;
   g.pcorr = P->pcorr;
+  g.cmean = P->cmean;
   return hip_check(launch_pseg(g, P->d.in_dtype, P->st), "per-chunk mean sums");
 }
 
@@ -1038,8 +1042,6 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   if (n_probes > 1 && pstride < 1) return fail(TACAW_ERR_INVALID_ARG, "probe_stride must be >= 1");
   if (((int64_t)P->N2 * fstride + P->span) * P->esz > (int64_t)0x7FFFFFFFLL)
     return fail(TACAW_ERR_UNSUPPORTED, "frame_stride too large for 31-bit row-group offsets");
-  if (P->d.mean_mode == TACAW_MEAN_PER_SEGMENT)
-    return fail(TACAW_ERR_UNSUPPORTED, "backward supports the global mean or none");
   if (P->H != P->L && 2 * P->H != P->L)
     return fail(TACAW_ERR_UNSUPPORTED, "backward supports hop = L or hop = L/2");
   if (!is_pow2(P->L)) return fail(TACAW_ERR_UNSUPPORTED, "backward needs a power-of-two seg_len");
@@ -1049,9 +1051,11 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   seg_fft_split(P->L, &n1b, &n2b);
   if (n1b != P->N1) return fail(TACAW_ERR_UNSUPPORTED, "table split mismatch");
   const bool global = P->d.mean_mode == TACAW_MEAN_GLOBAL;
+  const bool per_chunk = P->d.mean_mode == TACAW_MEAN_PER_SEGMENT;
   // the mean term comes from the forward pass's bin sums when the window's DFT
-  // lives on bins 0, +-1 (those sums exist); otherwise a second pass applies it
-  const int n_corr = (global && P->strategy == kRefFirstFrame) ? P->n_corr : 0;
+  // lives on bins 0, +-1 (those sums exist); otherwise a second pass applies it.
+  // Per-chunk means (compact windows only) are applied inside the kernel.
+  const int n_corr = ((global || per_chunk) && P->strategy == kRefFirstFrame) ? P->n_corr : 0;
   const int Wb = bwd_tile_pixels(P->L);
   const int n_tiles = (P->n_k + Wb - 1) / Wb;
   const int64_t need = (int64_t)n_probes * P->n_k * 16 + (int64_t)n_tiles * 16;
@@ -1078,6 +1082,8 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   b.n_om = P->n_om;
   b.roi_half = P->roi;
   b.mean_global = global ? 1 : 0;
+  b.per_chunk = per_chunk ? 1 : 0;
+  b.cmean = P->cmean;
   b.inv_nused = 1.0 / (double)P->n_used;
   b.n_used = P->n_used;
   b.win_t = P->win_t;
