@@ -120,14 +120,17 @@ __global__ void ring_store_kernel(const InT* in, int64_t pstride, int64_t fstrid
 // to R in absolute frame index) of 256 V / R pixels, so it reads R runs of 256 V / R pixels and
 // writes R consecutive rows, R W elements in a row, of each of its tiles: long
 // runs on both sides instead of one tile row (64 bytes at W = 8) per tile.
+#ifndef TACAW_RING_VEC
+#define TACAW_RING_VEC 16  // bytes each thread of the tiled ring store copies per frame
+#endif
 template <typename InT>
 __global__ void ring_store_tiled_kernel(const InT* in, int64_t pstride, int64_t fstride,
                                         int32_t nx, int64_t rs, int64_t push_begin, int64_t f_lo,
                                         int64_t f_hi, int32_t R, int32_t probe0, int32_t n_slots,
                                         int64_t depth, int32_t n_k, int32_t tile_w,
                                         int32_t n_tiles, InT* ring) {
-  constexpr int V = 16 / (int)sizeof(InT);  // elements per thread
-  const int tpr = 256 / R;                   // threads per frame
+  constexpr int V = TACAW_RING_VEC / (int)sizeof(InT);  // elements per thread
+  const int tpr = 256 / R;                               // threads per frame
   const int r = threadIdx.x / tpr;
   const int64_t k0 = ((int64_t)blockIdx.x * tpr + threadIdx.x % tpr) * V;
   const int64_t f = (f_lo - f_lo % R) + (int64_t)blockIdx.y * R + r;
@@ -149,8 +152,8 @@ hipError_t launch_ring_store(const void* in, int in_dtype, int64_t pstride, int6
                              hipStream_t st) {
   const int64_t nf = f_hi - f_lo;
   if (nf <= 0) return hipSuccess;
-  const int V = in_dtype == 1 ? 1 : 2;
   if (tile_w > 0) {
+    const int V = TACAW_RING_VEC / (in_dtype == 1 ? 16 : 8);
 #ifndef TACAW_RING_ROWS
 #define TACAW_RING_ROWS 16  // frames per block of the tiled ring store (tuning parameter)
 #endif
@@ -171,6 +174,7 @@ hipError_t launch_ring_store(const void* in, int in_dtype, int64_t pstride, int6
                          depth, n_k, tile_w, n_tiles, (float2*)ring);
     return hipGetLastError();
   }
+  const int V = in_dtype == 1 ? 1 : 2;
   dim3 g((unsigned)((n_k + 256 * V - 1) / (256 * V)), (unsigned)nf, n_probes);
   if (in_dtype == 1)
     hipLaunchKernelGGL(ring_store_kernel<double2>, g, dim3(256), 0, st, (const double2*)in,
