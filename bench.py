@@ -362,8 +362,9 @@ def main():
                                              "bwd_kernel_L512_16probes_counters.json"),
             "forward_chunk_kernel_ms": round(k_ms, 4),
             "note": "adjoint launch (bwd_kernel and the window-parameter reduction): reads "
-                    "psi once and writes dL/dpsi once (2 x exit-wave bytes); it recomputes "
-                    "each chunk's transform and runs a second one, so it is VALU-bound",
+                    "psi once and writes dL/dpsi once (2 x exit-wave bytes). HBM is its nearest "
+                    "roofline; it recomputes each chunk's transform and runs a second one, whose "
+                    "VALU issue and latency keep it below",
         }
     if args.form != "fft":
         tf = gemm_flops / (k_ms * 1e-3) / 1e12

@@ -510,6 +510,19 @@ int bwd_tile_pixels(int L) {
   return 0;
 }
 
+// pass-1 DFT size of the adjoint's split; it reads the plan's window and twiddle
+// tables, which are laid out for the forward split, so the two must agree
+int bwd_pass1_size(int L) {
+  switch (L) {
+    case 64: return BwdShape<64>::N1;
+    case 128: return BwdShape<128>::N1;
+    case 256: return BwdShape<256>::N1;
+    case 512: return BwdShape<512>::N1;
+    case 1024: return BwdShape<1024>::N1;
+  }
+  return 0;
+}
+
 hipError_t launch_bwd(int L, int in_dtype, const BwdArgs& a, int n_tiles, hipStream_t st) {
   switch (L) {
     case 64: return launch_bl<64>(in_dtype, a, n_tiles, st);

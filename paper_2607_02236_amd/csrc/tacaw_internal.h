@@ -183,6 +183,7 @@ struct BwdArgs {
 };
 hipError_t launch_bwd(int L, int in_dtype, const BwdArgs& a, int n_tiles, hipStream_t st);
 int bwd_tile_pixels(int L);
+int bwd_pass1_size(int L);
 hipError_t launch_bwd_mean_fix(const BwdArgs& a, int in_dtype, hipStream_t st);
 hipError_t launch_bwd_wparam(const double* part, int n, double c, double* out, hipStream_t st);
 hipError_t launch_mean_exact(const void* in, int in_dtype, int64_t pstride, int64_t fstride,

@@ -1047,9 +1047,8 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   if (!is_pow2(P->L)) return fail(TACAW_ERR_UNSUPPORTED, "backward needs a power-of-two seg_len");
   if ((gD || gDp) && P->d.n_det == 0)
     return fail(TACAW_ERR_INVALID_ARG, "detector gradients need plan masks");
-  int n1b = 0, n2b = 0;
-  seg_fft_split(P->L, &n1b, &n2b);
-  if (n1b != P->N1) return fail(TACAW_ERR_UNSUPPORTED, "table split mismatch");
+  if (bwd_pass1_size(P->L) != P->N1)
+    return fail(TACAW_ERR_UNSUPPORTED, "the adjoint's DFT split differs from the plan's tables");
   const bool global = P->d.mean_mode == TACAW_MEAN_GLOBAL;
   const bool per_chunk = P->d.mean_mode == TACAW_MEAN_PER_SEGMENT;
   // the mean term comes from the forward pass's bin sums when the window's DFT
