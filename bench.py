@@ -129,6 +129,8 @@ def main():
                          "pushed in pieces of --push-frames frames through the plan's ring; "
                          "gradient: 16 probes x 1024 frames x 128^2 c64, L=H=512, forward + "
                          "adjoint")
+    ap.add_argument("--hop", type=int, default=0,
+                    help="chunk hop of the realistic workload (default seg_len / 2)")
     ap.add_argument("--mean-mode", default="global", choices=["global", "per_segment", "none"],
                     help="elastic-mean handling (per_segment: each chunk's own mean)")
     ap.add_argument("--push-frames", type=int, default=256)
@@ -173,7 +175,7 @@ def main():
         n_pr = args.probes if args.probes != 64 else 16
         spec = T.config_streaming(n_probe=n_pr, n_frames=4096, ny=1024, nx=1024)
     else:
-        L, H = args.seg_len, args.seg_len // 2
+        L, H = args.seg_len, (args.hop or args.seg_len // 2)
         spec = T.config_realistic(n_probe=args.probes, n_frames=args.frames, ny=args.grid,
                                   nx=args.grid)
     streaming = args.workload == "streaming"
