@@ -290,6 +290,22 @@ def main():
         ceil_ms.append(c0.elapsed_time(c1))
     read_ceiling = psi.numel() * psi.element_size() / (float(np.median(ceil_ms)) * 1e-3) / 1e9
     log(f"read probe over {psi.numel() * psi.element_size() / 1e9:.1f} GB: {read_ceiling:.0f} GB/s")
+    # the same bytes in the chunk transform's pattern: tile-wide columns across frames
+    seg = plan.info()["tile_pixels"] * psi.element_size()
+    col_ms = []
+    if seg in (64, 128, 256, 512) and (spec.n_k * psi.element_size()) % seg == 0:
+        for _ in range(3):
+            c0 = torch.cuda.Event(enable_timing=True)
+            c1 = torch.cuda.Event(enable_timing=True)
+            c0.record(stream)
+            tacaw.read_probe_columns(psi, psi.shape[0] * psi.shape[1], seg, stream=stream)
+            c1.record(stream)
+            c1.synchronize()
+            col_ms.append(c0.elapsed_time(c1))
+    col_ceiling = (psi.numel() * psi.element_size() / (float(np.median(col_ms)) * 1e-3) / 1e9
+                   if col_ms else None)
+    if col_ceiling:
+        log(f"column read probe ({seg}-byte tiles): {col_ceiling:.0f} GB/s")
 
     b_alg = spec.nbytes  # each unique exit-wave value once
     value = b_alg / (ms * 1e-3) / 1e9
@@ -380,6 +396,10 @@ def main():
         }
     out["roofline"]["read_ceiling_gbs"] = round(read_ceiling, 1)
     out["roofline"]["value_frac_of_read_ceiling"] = round(value / read_ceiling, 4)
+    if col_ceiling and args.form == "fft" and not gradient:
+        # the chunk kernel's loads alone, in its own tile pattern: its HBM rate against that
+        out["roofline"]["tile_pattern_read_ceiling_gbs"] = round(col_ceiling, 1)
+        out["roofline"]["kernel_frac_of_tile_pattern_ceiling"] = round(achieved / col_ceiling, 4)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         del psi

@@ -278,6 +278,17 @@ const char* tacaw_version(void);
  * is allocated. Errors: INVALID_ARG, HIP. */
 int tacaw_read_probe(const void* d_buf, int64_t n_bytes, void* hip_stream, uint64_t* d_sum);
 
+/* The same measurement for the access pattern of the chunk transform: the
+ * device buffer is n_rows rows (frames) of row_bytes, read once column by
+ * column, seg_bytes wide (a pixel tile: 128 = 16 complex64 pixels), with 8-byte
+ * loads, so that one wave load takes seg_bytes from each of 512 / seg_bytes
+ * rows. *d_sum receives the same wrapping 64-bit sum as tacaw_read_probe gives
+ * for the whole buffer. seg_bytes in {64, 128, 256, 512}, row_bytes a multiple
+ * of it (at most 65535 columns), 8-byte alignment; nothing is allocated.
+ * Errors: INVALID_ARG, HIP. */
+int tacaw_read_probe_columns(const void* d_buf, int64_t n_rows, int64_t row_bytes,
+                             int32_t seg_bytes, void* hip_stream, uint64_t* d_sum);
+
 #ifdef __cplusplus
 }
 #endif

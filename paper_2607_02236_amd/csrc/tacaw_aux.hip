@@ -568,6 +568,52 @@ hipError_t launch_read_probe(const void* p, int64_t bytes, uint64_t* sum, hipStr
   return hipGetLastError();
 }
 
+// Column pattern, the chunk transform's loads without its arithmetic: the rows
+// (frames) of row_bytes are cut into columns seg_bytes wide (pixel tiles). One
+// 512-thread workgroup per column walks all rows; a thread takes 8 bytes,
+// seg_bytes / 8 lanes share a row, so a wave load spans 64 / (seg_bytes / 8) rows,
+// and 8 row passes are in flight. The workgroup reserves most of the LDS so
+// that, like the chunk transform, one runs per CU.
+constexpr int kColThreads = 512;
+constexpr int kColLds = 96 * 1024;
+__global__ void __launch_bounds__(kColThreads) read_probe_columns_kernel(
+    const char* __restrict__ p, int64_t n_rows, int64_t row_bytes, int32_t lanes,
+    unsigned long long* sum) {
+  constexpr int U = 8;
+  __shared__ unsigned long long red[kColLds / 8];  // only the first kColThreads are used
+  const int rows_per_pass = kColThreads / lanes;
+  const int lane = threadIdx.x % lanes, r_off = threadIdx.x / lanes;
+  const char* colp = p + (int64_t)blockIdx.x * lanes * 8 + lane * 8;
+  unsigned long long acc = 0;
+  for (int64_t r0 = r_off; r0 < n_rows; r0 += (int64_t)U * rows_per_pass) {
+    unsigned long long v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = r0 + (int64_t)u * rows_per_pass;
+      v[u] = r < n_rows ? *(const unsigned long long*)(colp + r * row_bytes) : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += v[u];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kColThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(sum, red[0]);
+}
+
+hipError_t launch_read_probe_columns(const void* p, int64_t n_rows, int64_t row_bytes,
+                                     int32_t seg_bytes, uint64_t* sum, hipStream_t st) {
+  hipError_t e = launch_fill_zero(sum, 8, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(read_probe_columns_kernel, dim3((unsigned)(row_bytes / seg_bytes)),
+                     dim3(kColThreads), 0, st, (const char*)p, n_rows, row_bytes,
+                     seg_bytes / 8, (unsigned long long*)sum);
+  return hipGetLastError();
+}
+
 // S[i] <- kappa q(r) S[i], row r = (i / inner) % n_om (q null: factor 1); copy to out if given
 __global__ void scale_copy_kernel(double* S, double* out, int64_t n, double kappa, const double* q,
                                   int64_t inner, int32_t n_om) {

@@ -81,6 +81,8 @@ hipError_t launch_gemm_scale(const void* in, int in_dtype, int64_t pstride, int6
 // Auxiliary kernels (tacaw_aux.hip).
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
 hipError_t launch_read_probe(const void* p, int64_t bytes, uint64_t* sum, hipStream_t st);
+hipError_t launch_read_probe_columns(const void* p, int64_t n_rows, int64_t row_bytes,
+                                     int32_t seg_bytes, uint64_t* sum, hipStream_t st);
 // nx, rs: pixel rows of the input frames (see pix_off)
 hipError_t launch_ref_first_frame(const void* in, int in_dtype, int64_t pstride, int32_t nx,
                                   int64_t rs, int32_t probe0, int32_t n_probes, int32_t n_k,

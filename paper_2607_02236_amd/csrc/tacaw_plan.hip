@@ -413,6 +413,23 @@ int tacaw_read_probe(const void* d_buf, int64_t n_bytes, void* hip_stream, uint6
   return hip_check(launch_read_probe(d_buf, n_bytes, d_sum, (hipStream_t)hip_stream), "read probe");
 }
 
+int tacaw_read_probe_columns(const void* d_buf, int64_t n_rows, int64_t row_bytes,
+                             int32_t seg_bytes, void* hip_stream, uint64_t* d_sum) {
+  g_err.clear();
+  if (!d_buf || !d_sum) return fail(TACAW_ERR_INVALID_ARG, "buffer and sum must not be NULL");
+  if (!(seg_bytes == 64 || seg_bytes == 128 || seg_bytes == 256 || seg_bytes == 512))
+    return fail(TACAW_ERR_INVALID_ARG, "seg_bytes must be 64, 128, 256 or 512");
+  if (n_rows < 1 || row_bytes < seg_bytes || row_bytes % seg_bytes != 0)
+    return fail(TACAW_ERR_INVALID_ARG, "row_bytes must be a positive multiple of seg_bytes");
+  if (row_bytes / seg_bytes > 65535)
+    return fail(TACAW_ERR_INVALID_ARG, "at most 65535 columns");
+  if (((uintptr_t)d_buf) % 8 != 0 || ((uintptr_t)d_sum) % 8 != 0)
+    return fail(TACAW_ERR_INVALID_ARG, "buffer and sum must be 8-byte aligned");
+  return hip_check(launch_read_probe_columns(d_buf, n_rows, row_bytes, seg_bytes, d_sum,
+                                             (hipStream_t)hip_stream),
+                   "column read probe");
+}
+
 int tacaw_plan_check(const tacaw_plan_desc* d) {
   g_err.clear();
   if (!d) return fail(TACAW_ERR_INVALID_ARG, "desc is NULL");

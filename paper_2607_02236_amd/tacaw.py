@@ -80,6 +80,7 @@ def _load():
         "tacaw_last_error": (C.c_char_p, []),
         "tacaw_version": (C.c_char_p, []),
         "tacaw_read_probe": (C.c_int, [P, C.c_int64, P, P]),
+        "tacaw_read_probe_columns": (C.c_int, [P, C.c_int64, C.c_int64, C.c_int32, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -93,7 +94,7 @@ EXPORTED = ("tacaw_plan", "tacaw_plan_check", "tacaw_push_frames", "tacaw_ingest
             "tacaw_commit_frames", "tacaw_finalize",
             "tacaw_detector_spectra", "tacaw_backward", "tacaw_reset", "tacaw_set_stream",
             "tacaw_plan_get_info", "tacaw_destroy", "tacaw_last_error", "tacaw_version",
-            "tacaw_read_probe")
+            "tacaw_read_probe", "tacaw_read_probe_columns")
 
 
 def _check(rc):
@@ -350,4 +351,23 @@ def read_probe(buf: torch.Tensor, out: torch.Tensor | None = None, stream=None) 
     s, sptr = _stream_ptr(stream)
     _check(lib.tacaw_read_probe(C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(), sptr,
                                 C.c_void_p(out.data_ptr())))
+    return out
+
+
+def read_probe_columns(buf: torch.Tensor, rows: int, seg_bytes: int = 128,
+                       out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Read a contiguous CUDA tensor, seen as `rows` equal rows (frames), once in the
+    chunk transform's access pattern (columns seg_bytes wide across the rows);
+    returns the wrapping 64-bit word sum."""
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("read_probe_columns needs a contiguous CUDA tensor")
+    nbytes = buf.numel() * buf.element_size()
+    if rows < 1 or nbytes % rows != 0:
+        raise ValueError("rows must divide the tensor's bytes")
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=buf.device)
+    row_bytes = nbytes // rows
+    s, sptr = _stream_ptr(stream)
+    _check(lib.tacaw_read_probe_columns(C.c_void_p(buf.data_ptr()), rows, row_bytes, int(seg_bytes),
+                                        sptr, C.c_void_p(out.data_ptr())))
     return out
