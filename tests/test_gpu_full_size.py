@@ -1,6 +1,6 @@
 """Parity at the full workload sizes, in the launch configuration bench.py times
-(one whole-series push), on outputs the oracle computes pixel by pixel: S and the
-gradient at seeded sampled pixels (every probe, every frame), regenerated
+(one whole-series push), on outputs the oracle computes pixel by pixel: S (global
+and per-chunk mean) and the gradient at seeded sampled pixels (every probe, every frame), regenerated
 bit-identically on the CPU; detector spectra through properties that hold at any
 size (D equals a float64 reduction of the GPU's S; the probe mean of D_p is D)."""
 
@@ -41,10 +41,20 @@ def test_realistic_workload_64_probes_256sq():
     plan.push(psi)
     S = plan.finalize()
     D, Dp = plan.detector_spectra(per_probe=True)
+    # the per-chunk mean on the same resident series
+    pseg = tacaw.Plan(spec.n_probe, 256, 256, spec.n_frames, L, H, mean_mode="per_segment")
+    pseg.push(psi)
+    S_seg = pseg.finalize()
     torch.cuda.synchronize()
+    pseg.close()
     del psi
     pix = np.sort(np.random.default_rng(8).choice(256 * 256, size=48, replace=False))
-    So, _ = O.tacaw_spectra_fft(T.generate(spec, pixels=pix).numpy(), L, H, O.window("hann", L))
+    sample = T.generate(spec, pixels=pix).numpy()
+    So, _ = O.tacaw_spectra_fft(sample, L, H, O.window("hann", L))
+    Sso, _ = O.tacaw_spectra_fft(sample, L, H, O.window("hann", L), "per_segment")
+    es = rel(S_seg.reshape(L, -1)[:, torch.from_numpy(pix).cuda()].cpu().numpy(), Sso)
+    print(f"64 probes 256^2, per-chunk mean: S(sampled) {es:.2e}", flush=True)
+    assert es <= 1e-5
     e = rel(S.reshape(L, -1)[:, torch.from_numpy(pix).cuda()].cpu().numpy(), So)
     Dref = torch.einsum("jk,mk->jm", masks.reshape(4, -1), S.reshape(L, -1))
     eD = max(rel(D[j].cpu(), Dref[j].cpu()) for j in range(4))
