@@ -367,11 +367,12 @@ __global__ void __launch_bounds__(256) pseg_kernel(const PsegArgs a) {
     }
   };
   if constexpr (FAST) {
-    // H divides L (FAST is chosen when L = V H): frame n = j H + u lies in chunks j - q, q = 0..V-1, at
-    // t = q H + u, so inside a hop block every frame updates the same V sums
-    // with no bookkeeping; chunk j starts at u = 0 and chunk j - V + 1 ends
-    // after u = H - 1. Register sq[q] holds chunk j - q (HBM slot (j - q) mod V);
-    // sums of chunks that do not exist (j - q < 0) are never closed.
+    // H divides L (FAST is chosen when L = V H): frame n = j H + u lies in chunks
+    // j - q, q = 0..V-1, at t = q H + u, so inside a hop block every frame updates
+    // the same V sums with no bookkeeping; chunk j starts at u = 0 and chunk
+    // j - V + 1 ends after u = H - 1. Register sq[q] holds chunk j - q (HBM slot
+    // (j - q) mod V); sums of chunks that do not exist (j - q < 0, or past the
+    // last chunk) are never closed.
     double2 sq[V][Q];
     const int jb = (int)(a.f_lo / a.H);
 #pragma unroll
