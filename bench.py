@@ -34,6 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # x 2 flops x 2.4 GHz (the chip's packed-FP32 figure, 157.3 TFLOP/s, needs packed instructions,
 # which this build disables)
 VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+FP32_PEAK_TFLOPS = 157.3  # published FP32 vector peak of MI355X (packed)
 
 
 def fft_flops_per_element(L, H):
@@ -351,22 +352,30 @@ def main():
             "seg_len": L, "hop": H, "n_omega": n_om, "exit_wave_bytes": b_alg,
         },
         "roofline": {
-            "bound": "alu",
+            "bound": "hbm",
             "kernel": "seg_fft_kernel",
-            "achieved": round(alu_tf, 2),
-            "peak": round(VALU_PEAK_TFLOPS, 1),
-            "unit": "TFLOP/s",
-            "frac": round(alu_tf / VALU_PEAK_TFLOPS, 4),
-            "kernel_ms": round(k_ms, 4),
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic_from_profiles(ksrc, run_cfg),
-            "flops_per_element": round(fft_flops_per_element(L, H), 2),
-            "hbm_achieved_gbs": round(achieved, 2),
-            "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
-            "note": "the chunk kernel is bound by non-packed FP32 VALU issue (about 32 VALU "
-                    "instructions per point and transform, VALU busy ~67% at two waves per "
-                    "SIMD), not by HBM: its HBM traffic is ~1.02x the algorithmic bytes and "
-                    "reaches hbm_frac of 8 TB/s. achieved = algorithmic flops "
-                    "(flops_per_element x elements) / kernel time",
+            "kernel_ms": round(k_ms, 4),
+            "algorithmic_bytes_per_launch": b_alg,
+            "note": "achieved = algorithmic bytes of one launch (every exit-wave value once: "
+                    "probes x frames x pixels x 8 B) / the chunk kernel's average launch time "
+                    "(HIP events on the plan's stream); traffic = HBM bytes per launch from "
+                    "rocprofv3 FETCH_SIZE/WRITE_SIZE (null unless taken on these kernel sources "
+                    "and this workload)",
+            "flops": {
+                "per_element": round(fft_flops_per_element(L, H), 2),
+                "achieved_tflops": round(alu_tf, 2),
+                "frac_of_fp32_157_3": round(alu_tf / FP32_PEAK_TFLOPS, 4),
+                "frac_of_fp32_nonpacked_78_6": round(alu_tf / VALU_PEAK_TFLOPS, 4),
+                "note": "algorithmic flops (per_element x elements) / kernel time, against the "
+                        "published 157.3 TFLOP/s FP32 peak (packed instructions) and the "
+                        "78.6 TFLOP/s the non-packed FMAs this build issues can reach "
+                        "(256 CU x 64 lanes x 2 flops x 2.4 GHz)",
+            },
         },
     }
     if gradient:

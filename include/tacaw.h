@@ -178,8 +178,8 @@ int tacaw_plan_check(const tacaw_plan_desc* desc);
  * not depend on how frames or probes are split into pushes (App. B: batch shape
  * does not influence the results). A thermalisation period is discarded by
  * pointing d_frames at the first kept frame, and every s-th stored snapshot
- * is kept by passing s times the frame pitch as frame_stride (Sec. IV drops
- * the first picoseconds of each trajectory); no copy is made.
+ * is kept by passing s times the frame pitch as frame_stride (Sec. III.A drops
+ * the first picoseconds of each trajectory before chunking); no copy is made.
  * Errors: INVALID_ARG (null/misaligned pointer, bad stride), SHAPE (probe range
  * or frame count beyond the plan), STATE (plan finalized, probes at different
  * frame cursors, ring capacity exceeded), OOM, HIP. */
@@ -204,9 +204,8 @@ int tacaw_push_frames(tacaw_plan_t plan, const void* d_frames, int32_t probe0, i
 int tacaw_ingest_frames(tacaw_plan_t plan, int32_t probe0, int32_t n_probes, int64_t n_frames,
                         void** d_dst, int64_t* probe_stride, int64_t* frame_stride);
 
-/* Mark the frames handed out by the open tacaw_ingest_frames as written: the
- * reference of a probe's first frame is taken and, at the end of a series, its
- * remaining chunks run. Errors: STATE (no matching ingest), HIP. */
+/* Mark the frames handed out by the open tacaw_ingest_frames as written: at the
+ * end of a series, its remaining chunks run. Errors: STATE (no matching ingest), HIP. */
 int tacaw_commit_frames(tacaw_plan_t plan, int32_t probe0, int32_t n_probes, int64_t n_frames);
 
 /* Finish the reduction once every probe's series has been pushed: applies the

@@ -5,11 +5,12 @@
 //
 // What is computed (paper Sec. II.B.2 and Eq. 1, 2): for chunk s of probe p and
 // pixel k, X'_s(m, k) = sum_t w(t) (psi(sH + t, k) - c(k)) exp(-2 pi i m t / L),
-// and S(m, k) += |X'_s(m, k)|^2. c is a per-(probe, pixel) reference (the first
-// frame, or the exact mean); the difference to the elastic mean mu is restored
-// exactly afterwards from FP64 sums (finalize), because for the supported
-// compact windows W(m) = sum_t w(t) exp(-2 pi i m t / L) vanishes outside bins
-// {0, 1, L-1}.
+// and S(m, k) += |X'_s(m, k)|^2. c is a per-(probe, pixel) reference (a
+// window-weighted mean of frames sampled over the first chunk, or the exact
+// mean); the difference to the elastic mean mu is restored exactly afterwards
+// from FP64 sums (finalize), because for the supported compact windows
+// W(m) = sum_t w(t) exp(-2 pi i m t / L) vanishes outside bins {0, 1, L-1}.
+// At those bins |X'|^2 is squared in FP64 (the correction cancels most of it).
 //
 // Work decomposition (one workgroup = a tile of W adjacent pixels, all probes
 // and all chunks of the push):
@@ -31,6 +32,14 @@
 #include "tacaw_internal.h"
 
 namespace tacaw {
+
+// |z|^2 in FP64. At the correction bins the exact mean correction cancels most of
+// sum_s |X'_s|^2, so it is formed from the FP32 transform values without the
+// FP32 rounding of the square.
+__device__ __forceinline__ double sq64(float2 z) {
+  const double x = (double)z.x, y = (double)z.y;
+  return x * x + y * y;
+}
 
 template <int L>
 struct FftShape;
@@ -117,6 +126,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
   __shared__ float2 s_tw[L];          // [n2][k1]
   __shared__ float s_win[L];          // [n2][n1]
   __shared__ double s_mask[DP ? kMaxDet * W : 1];
+  __shared__ double2 s_ref[W];        // reference of the probe's pixels (first chunk)
 
   const int tid = threadIdx.x;
   const int px = tid % W;
@@ -220,8 +230,10 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
   int cc = 0;  // chunks processed by this thread block (selects the exchange tile)
   for (int i = 0; i < a.n_probes; ++i) {
     const int p = a.probe0 + i;
-    const double2 cr = a.cref[(int64_t)p * n_k + kc];
-    const float2 cf = make_float2((float)cr.x, (float)cr.y);
+    // reference c: fixed by the probe's first chunk (make_ref below) or read back
+    double2 cr = make_double2(0.0, 0.0);
+    if (!(track && a.s_lo == 0)) cr = a.cref[(int64_t)p * n_k + kc];
+    float2 cf = make_float2((float)cr.x, (float)cr.y);
     const char* in_probe = (const char*)a.in + (int64_t)i * a.pstride * ESZ;
     const InT* ringb =
         a.ring ? (const InT*)a.ring + ((int64_t)(p % a.n_slots) * a.ring_depth) * n_k + kc : nullptr;
@@ -262,6 +274,52 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
           msum.y += count ? dy : 0.0;
         }
         return z;
+      };
+      // The probe's first chunk fixes c: the window-weighted mean of the N1 frames
+      // t = N2 n1 + N2 / 2, spread evenly over the chunk, which thread n2 = N2 / 2
+      // holds (FP64 sum, rounded to FP32 for complex64 input so that the FP32
+      // subtraction below is exact). Every value of c keeps the mean correction
+      // exact; one near the chunks' own mean keeps |X'| small at bins 0 and +-1,
+      // where the correction cancels. It depends only on the series, not on how
+      // it was pushed.
+      // raw(n1): the thread's raw sample n1 of the chunk, from a register array
+      // (unrolled loop) or a load (rolled loop: once per probe, few registers)
+      auto make_ref = [&](auto raw, auto unroll) {
+        if (n2 == N2 / 2) {
+          double sx = 0.0, sy = 0.0, sw = 0.0, px_ = 0.0, py_ = 0.0;
+          auto add = [&](int n1) {
+            const InT x = raw(n1);
+            const double w = fabs((double)s_win[n2 * N1 + n1]);
+            sx += w * (double)x.x;
+            sy += w * (double)x.y;
+            px_ += (double)x.x;
+            py_ += (double)x.y;
+            sw += w;
+          };
+          if constexpr (decltype(unroll)::value) {
+#pragma unroll
+            for (int n1 = 0; n1 < N1; ++n1) add(n1);
+          } else {
+#pragma unroll 1
+            for (int n1 = 0; n1 < N1; ++n1) add(n1);
+          }
+          if (!(sw > 0.0)) {  // a window that vanishes at every sample: plain mean
+            sx = px_;
+            sy = py_;
+            sw = (double)N1;
+          }
+          sx /= sw;
+          sy /= sw;
+          if constexpr (ESZ == 8) {
+            sx = (double)(float)sx;
+            sy = (double)(float)sy;
+          }
+          s_ref[px] = make_double2(sx, sy);
+          if (kvalid) a.cref[(int64_t)p * n_k + k] = make_double2(sx, sy);
+        }
+        __syncthreads();
+        cr = s_ref[px];
+        cf = make_float2((float)cr.x, (float)cr.y);
       };
       auto fetch_fast = [&](int n1) -> InT {
         // uniform base of the row group N2 * n1 .. N2 * n1 + N2 - 1 of this chunk;
@@ -310,6 +368,7 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
         } else if (!track) {
           take_pre(0, C0{});
         } else if (s == 0 || FULL) {
+          if (s == 0) make_ref([&](int n1) { return pre[n1]; }, std::true_type{});
           take_pre(0, C1{});
         } else {
           take_pre(0, C3{});
@@ -339,6 +398,8 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
           if (fast) load_range(0, fetch_fast, C0{});
           else load_range(0, fetch_any, C0{});
         } else if (s == 0) {
+          // thread n2 = N2 / 2 loads its samples for the reference (and again below)
+          make_ref(fetch_any, std::false_type{});
           if (fast) load_range(0, fetch_fast, C1{});
           else load_range(0, fetch_any, C1{});
         } else {
@@ -388,17 +449,26 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
           dft_inplace<N2>(X);
 #pragma unroll
           for (int k2 = 0; k2 < N2; ++k2) {
-            const float pw = X[k2].x * X[k2].x + X[k2].y * X[k2].y;
-            acc[q * N2 + k2] += (double)pw;
+            // the correction bins (bin 0, 1: q = 0, k2 = 0 of threads j = 0, 1; bin
+            // L - 1: q = R - 1, k2 = N2 - 1 of thread j = N2 - 1) are added below
+            const bool cand = (q == 0 && k2 == 0) || (q == R - 1 && k2 == N2 - 1);
+            if (!(cand && corr_own && (k2 == 0 ? j <= 1 : j == N2 - 1 && j > 1))) {
+              const float pw = X[k2].x * X[k2].x + X[k2].y * X[k2].y;
+              acc[q * N2 + k2] += (double)pw;
+            }
           }
+          // (the correction bins: their FP64 sum, and their square in FP64 unless
+          // the per-chunk mean kernel supplies them)
           if (corr_own) {
             if (q == 0 && j <= 1) {
               xsum.x += (double)X[0].x;
               xsum.y += (double)X[0].y;
+              if (!a.corr_skip) acc[0] += sq64(X[0]);
             }
             if (q == R - 1 && j == N2 - 1 && j > 1) {
               xsum.x += (double)X[N2 - 1].x;
               xsum.y += (double)X[N2 - 1].y;
+              if (!a.corr_skip) acc[q * N2 + N2 - 1] += sq64(X[N2 - 1]);
             }
           }
         }
@@ -453,16 +523,24 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
         dft_inplace<N1>(X);
 #pragma unroll
         for (int r = 0; r < N1; ++r) {
-          const float pw = X[r].x * X[r].x + X[r].y * X[r].y;
-          acc[r] += (double)pw;
+          // correction bins: r = 0 of threads j = 0, 1 (bins 0, 1) and r = N1 - 1 of
+          // thread j = N2 - 1 (bin L - 1) are added below
+          if (!((r == 0 || r == N1 - 1) && corr_own && (r == 0 ? j <= 1 : j > 1))) {
+            const float pw = X[r].x * X[r].x + X[r].y * X[r].y;
+            acc[r] += (double)pw;
+          }
         }
+        // (the correction bins: their FP64 sum, and their square in FP64 unless the
+        // per-chunk mean kernel supplies them)
         if (corr_own) {
           if (j <= 1) {
             xsum.x += (double)X[0].x;
             xsum.y += (double)X[0].y;
+            if (!a.corr_skip) acc[0] += sq64(X[0]);
           } else {
             xsum.x += (double)X[N1 - 1].x;
             xsum.y += (double)X[N1 - 1].y;
+            if (!a.corr_skip) acc[N1 - 1] += sq64(X[N1 - 1]);
           }
         }
       }

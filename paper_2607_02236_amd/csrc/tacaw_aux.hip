@@ -32,26 +32,44 @@ hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Reference c(k) of a probe: the window-weighted mean of up to kRefSamples
+// frames spread over the first chunk (FP64 sum, rounded to FP32 for complex64
+// input so that the chunk kernel subtracts exactly this value). Any c keeps the
+// mean correction exact; one close to the chunks' own mean keeps the FP32
+// transform of psi - c small at bins 0 and +-1, where the correction cancels.
 template <typename InT>
-__global__ void ref_first_kernel(const InT* in, int64_t pstride, int32_t nx, int64_t rs,
-                                 int32_t probe0, int32_t n_probes, int32_t n_k, double2* cref) {
+__global__ void ref_sampled_kernel(const InT* in, int64_t pstride, int64_t fstride, int32_t nx,
+                                   int64_t rs, RefSamples smp, int32_t probe0, int32_t n_probes,
+                                   int32_t n_k, double2* cref) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
   if (k >= n_k || i >= n_probes) return;
-  const InT v = in[(int64_t)i * pstride + pix_off(k, nx, rs)];
-  cref[(int64_t)(probe0 + i) * n_k + k] = make_double2((double)v.x, (double)v.y);
+  const InT* src = in + (int64_t)i * pstride + pix_off(k, nx, rs);
+  double sx = 0.0, sy = 0.0;
+  for (int r = 0; r < smp.n; ++r) {
+    const InT v = src[(int64_t)smp.t[r] * fstride];
+    sx += smp.wt[r] * (double)v.x;
+    sy += smp.wt[r] * (double)v.y;
+  }
+  sx *= smp.inv_sum;
+  sy *= smp.inv_sum;
+  if (smp.round32) {
+    sx = (double)(float)sx;
+    sy = (double)(float)sy;
+  }
+  cref[(int64_t)(probe0 + i) * n_k + k] = make_double2(sx, sy);
 }
 
-hipError_t launch_ref_first_frame(const void* in, int in_dtype, int64_t pstride, int32_t nx,
-                                  int64_t rs, int32_t probe0, int32_t n_probes, int32_t n_k,
-                                  double2* cref, hipStream_t st) {
+hipError_t launch_ref_sampled(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
+                              int32_t nx, int64_t rs, const RefSamples& smp, int32_t probe0,
+                              int32_t n_probes, int32_t n_k, double2* cref, hipStream_t st) {
   dim3 g((n_k + 255) / 256, n_probes);
   if (in_dtype == 1)
-    hipLaunchKernelGGL(ref_first_kernel<double2>, g, dim3(256), 0, st, (const double2*)in,
-                       pstride, nx, rs, probe0, n_probes, n_k, cref);
+    hipLaunchKernelGGL(ref_sampled_kernel<double2>, g, dim3(256), 0, st, (const double2*)in,
+                       pstride, fstride, nx, rs, smp, probe0, n_probes, n_k, cref);
   else
-    hipLaunchKernelGGL(ref_first_kernel<float2>, g, dim3(256), 0, st, (const float2*)in, pstride,
-                       nx, rs, probe0, n_probes, n_k, cref);
+    hipLaunchKernelGGL(ref_sampled_kernel<float2>, g, dim3(256), 0, st, (const float2*)in,
+                       pstride, fstride, nx, rs, smp, probe0, n_probes, n_k, cref);
   return hipGetLastError();
 }
 
@@ -311,9 +329,9 @@ hipError_t launch_correct_Dp(const CorrArgs& c, const double* masks, int32_t n_d
 // ---- per-chunk mean --------------------------------------------------------
 // With its own mean mu_s subtracted, chunk s has at a correction bin b
 //   X_s(b) = A_s(b) - delta_s W(b),  A_s(b) = sum_t w(t) e^{-2 pi i b t / L} y'(s H + t),
-// where y' = psi - c is what the chunk kernel transforms and delta_s = mu_s - c
-// = (1/L) sum_t y'(s H + t). The chunk kernel accumulates |A_s(b)|^2, so the
-// correction is sum_s [-2 Re(conj(delta_s W(b)) A_s(b)) + |delta_s W(b)|^2].
+// where y' = psi - c and delta_s = mu_s - c = (1/L) sum_t y'(s H + t). The chunk
+// kernel leaves these bins out of S in this mode; this kernel adds the whole
+// sum_s |X_s(b)|^2, formed in FP64 from exact FP64 sums.
 // One thread per (probe, pixel) walks the push's frames in time order; the V
 // chunks that can hold a frame live in V register slots (chunk s in slot s mod V),
 // a chunk's sums are cleared at its first frame and turned into its correction
@@ -362,7 +380,8 @@ __global__ void __launch_bounds__(256) pseg_kernel(const PsegArgs a) {
       if (b == 0 || three) {
         const double2 wb = a.wbin[b];
         const double wx = dx * wb.x - dy * wb.y, wy = dx * wb.y + dy * wb.x;
-        cor[b] += -2.0 * (wx * A[b].x + wy * A[b].y) + (wx * wx + wy * wy);
+        const double xr = A[b].x - wx, xi = A[b].y - wy;  // X_s(b) = A_s(b) - delta_s W(b)
+        cor[b] += xr * xr + xi * xi;
       }
     }
   };

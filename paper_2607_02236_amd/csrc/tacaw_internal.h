@@ -39,10 +39,13 @@ struct SegArgs {
   int32_t s_lo, s_hi;      // chunks [s_lo, s_hi) are completed by this push
   int32_t hop;
   int32_t track_mean;      // accumulate sum(psi - c) and sum_s X'_s at the correction bins
+  int32_t corr_skip;       // leave the correction bins out of S (the per-chunk mean kernel
+                           // supplies their whole FP64 value)
   int32_t n_corr;          // 1 (rectangular) or 3 (Hann)
   const float* win_t;      // window, transposed per thread: [N2][N1] (t = N2*n1 + n2)
   const float2* tw;        // inter-pass twiddles exp(-2 pi i n2 k1 / L): [N2][N1]
-  const double2* cref;     // [n_probe][n_k] reference subtracted before the window
+  double2* cref;           // [n_probe][n_k] reference subtracted before the window; with
+                           // track_mean the launch holding a probe's first chunk writes it
   double2* msum;           // [n_probe][n_k] FP64 sum of (psi - c) over counted frames
   double2* xs;             // [n_probe][kMaxCorr][n_k] FP64 sum over chunks of X'(bin)
   double* S;               // [n_om][n_k] FP64 accumulator of sum |X'|^2
@@ -83,10 +86,20 @@ hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
 hipError_t launch_read_probe(const void* p, int64_t bytes, uint64_t* sum, hipStream_t st);
 hipError_t launch_read_probe_columns(const void* p, int64_t n_rows, int64_t row_bytes,
                                      int32_t seg_bytes, uint64_t* sum, hipStream_t st);
+// frames sampled for a probe's reference: frame t[r] of the push (relative to its
+// first frame) with weight wt[r]; c = inv_sum * sum_r wt[r] psi(t[r])
+constexpr int kRefSamples = 16;
+struct RefSamples {
+  int32_t n;
+  int32_t round32;  // round c to FP32 (complex64 input: the chunk kernel subtracts in FP32)
+  int32_t t[kRefSamples];
+  double wt[kRefSamples];
+  double inv_sum;
+};
 // nx, rs: pixel rows of the input frames (see pix_off)
-hipError_t launch_ref_first_frame(const void* in, int in_dtype, int64_t pstride, int32_t nx,
-                                  int64_t rs, int32_t probe0, int32_t n_probes, int32_t n_k,
-                                  double2* cref, hipStream_t st);
+hipError_t launch_ref_sampled(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
+                              int32_t nx, int64_t rs, const RefSamples& smp, int32_t probe0,
+                              int32_t n_probes, int32_t n_k, double2* cref, hipStream_t st);
 hipError_t launch_ref_mean(const void* in, int in_dtype, int64_t pstride, int64_t fstride,
                            int32_t nx, int64_t rs, int64_t n_used, int32_t probe0,
                            int32_t n_probes, int32_t n_k, double2* cref, hipStream_t st);
@@ -113,7 +126,7 @@ struct CorrArgs {
   const double2* cref;
   const double2* msum;
   const double2* xs;
-  const double* pcorr;  // [P][3][n_k] per-chunk-mean corrections (null unless that mode)
+  const double* pcorr;  // [P][3][n_k] per-chunk mean: sum_s |X_s(b)|^2 (null unless that mode)
 };
 // S[i] <- kappa * q[(i / inner) % n_om] * S[i] (q may be null), copied to out when given
 hipError_t launch_finalize_S(double* S, double* out, int64_t n_elem, double kappa, const double* q,
@@ -134,9 +147,9 @@ struct PsegArgs {
   int32_t L, H, Ns, n_corr, V;
   double2 wbin[kMaxCorr];  // W(bin)
   const double2* tw;       // [3][L]: w(t) exp(-2 pi i bin t / L), bins 0, 1, L - 1 (rows 0, 1 read)
-  const double2* cref;     // [P][n_k] reference c
+  const double2* cref;     // [P][n_k] reference c of these FP64 sums (the first frame)
   double2* open;           // [P][V][4][n_k]: open chunk sums (layout in pseg_kernel)
-  double* pcorr;           // [P][3][n_k]
+  double* pcorr;           // [P][3][n_k]: sum_s |X_s(b)|^2 of the closed chunks
   double2* cmean;          // [P][Ns][n_k]: each chunk's FP64 mean c + sum_t y' / L
 };
 hipError_t launch_pseg(const PsegArgs& a, int32_t in_dtype, hipStream_t st);
@@ -169,7 +182,7 @@ struct BwdArgs {
   const float* win_t;      // [N2][N1]
   const float* dwin_t;     // [N2][N1] d w / d r (HANN_WIDTH) or null
   const float2* tw;        // [N2][N1]
-  const double2* cref;     // [n_probe][n_k] reference c (first frame or exact mean)
+  const double2* cref;     // [n_probe][n_k] reference c (the chunk kernel's, or the exact mean)
   const double2* msum;     // [n_probe][n_k] FP64 sum over the used frames of psi - c
   const double2* xs;       // [n_probe][kMaxCorr][n_k] FP64 sum over chunks of X' at bins 0, 1, L-1
   int32_t n_corr;          // bins where the window's DFT is nonzero (1 or 3), 0 = any bin

@@ -29,7 +29,8 @@ constexpr int64_t kMaxDeviceBytes = (int64_t)260 << 30;  // refuse plans beyond 
 constexpr int kMaxTimed = 2;  // chunk launches per push (deferred mode: before and after the store)
 
 enum MeanStrategy {
-  kRefFirstFrame = 0,  // c = frame 0, exact correction at finalize (compact windows)
+  kRefSampled = 0,     // c = windowed mean of frames sampled over the first chunk, exact
+                       // correction at finalize (compact windows)
   kRefExactMean = 1,   // c = exact FP64 mean from a pre-pass over the whole series
   kRefZero = 2,        // c = 0 (mean NONE with a non-compact window)
 };
@@ -162,8 +163,9 @@ struct tacaw_plan_s {
   int bins[kMaxCorr] = {0, 0, 0};  // correction bins 0, 1, L-1 and their output rows
   int rows[kMaxCorr] = {0, 0, 0};
   double2 wbin[kMaxCorr];
+  std::vector<double> win;  // w(t), t = 0..L-1
   bool compact = false;
-  int strategy = kRefFirstFrame;
+  int strategy = kRefSampled;
   int esz = 8;
   int state = 0;  // 0 open, 1 finalized
   int64_t dropped = 0;
@@ -183,7 +185,8 @@ struct tacaw_plan_s {
   double2* xs = nullptr;    // [P][3][n_k]
   double2* pseg_tw = nullptr;    // per-chunk mean: [3][L] w(t) exp(-2 pi i bin t / L)
   double2* pseg_open = nullptr;  // per-chunk mean: [P][V][4][n_k] open chunk sums
-  double* pcorr = nullptr;       // per-chunk mean: [P][3][n_k] corrections
+  double* pcorr = nullptr;       // per-chunk mean: [P][3][n_k] sum_s |X_s(b)|^2
+  double2* pref = nullptr;       // per-chunk mean: [P][n_k] reference of its FP64 sums
   double2* cmean = nullptr;      // per-chunk mean: [P][Ns][n_k] chunk means (for the adjoint)
   int pseg_V = 0;                // chunks that can hold one frame, ceil(L / H)
   double* S = nullptr;      // [n_om][n_k]
@@ -263,6 +266,18 @@ static int hip_check(hipError_t e, const char* what) {
 
 static bool transform_is_gemm(int t) { return t == TACAW_GEMM_BF16X3 || t == TACAW_GEMM_F16X3; }
 
+// The per-chunk mean sums are formed in FP64 relative to a probe's first frame
+// (they run on every push, before the chunk kernel fixes its own reference).
+static RefSamples first_frame_sample() {
+  RefSamples r{};
+  r.n = 1;
+  r.t[0] = 0;
+  r.wt[0] = 1.0;
+  r.inv_sum = 1.0;
+  r.round32 = 0;
+  return r;
+}
+
 // One chunk-kernel launch over chunks [s_lo, s_hi) of probes [probe0, probe0 + n_probes),
 // followed by the per-probe detector partial reduce. from_ring: every frame is read from
 // the ring (deferred mode); otherwise from the push buffer `src` (frame push_begin at its
@@ -289,7 +304,8 @@ static int run_chunks(tacaw_plan_t P, const void* src, int64_t pstride, int64_t 
   g.s_lo = s_lo;
   g.s_hi = s_hi;
   g.hop = P->H;
-  g.track_mean = P->strategy == kRefFirstFrame ? 1 : 0;
+  g.track_mean = P->strategy == kRefSampled ? 1 : 0;
+  g.corr_skip = P->pcorr ? 1 : 0;
   g.n_corr = P->n_corr;
   g.win_t = P->win_t;
   g.tw = P->tw;
@@ -538,6 +554,7 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   // window, its DFT at every bin (FP64), and the correction bins
   std::vector<double> w = make_window(d->window, P->L, d->window_param);
   if (d->window == TACAW_WIN_CUSTOM) w.assign(d->h_window, d->h_window + P->L);
+  P->win = w;
   P->sumw2 = 0.0;
   double sumw = 0.0;
   for (double x : w) {
@@ -574,16 +591,16 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   if (gemm)  // the GEMM form subtracts the exact mean (or zero) before splitting
     P->strategy = d->mean_mode == TACAW_MEAN_GLOBAL ? kRefExactMean : kRefZero;
   else if (P->compact)
-    P->strategy = kRefFirstFrame;
+    P->strategy = kRefSampled;
   else
     P->strategy = d->mean_mode == TACAW_MEAN_GLOBAL ? kRefExactMean : kRefZero;
 
-  if (d->mean_mode == TACAW_MEAN_PER_SEGMENT && P->strategy != kRefFirstFrame) {
+  if (d->mean_mode == TACAW_MEAN_PER_SEGMENT && P->strategy != kRefSampled) {
     delete P;
     return fail(TACAW_ERR_UNSUPPORTED,
                 "per-segment mean needs a window whose DFT is confined to bins 0 and +-1");
   }
-  if (P->deferred && P->strategy != kRefFirstFrame) {
+  if (P->deferred && P->strategy != kRefSampled) {
     delete P;
     return fail(TACAW_ERR_UNSUPPORTED,
                 "deferred ring mode needs a window whose DFT is confined to bins 0 and +-1");
@@ -628,6 +645,7 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
     A((void**)&P->pseg_tw, (int64_t)kMaxCorr * P->L * 16, "per-chunk mean twiddles");
     A((void**)&P->pseg_open, np * P->pseg_V * (1 + kMaxCorr) * nk * 16, "open chunk sums");
     A((void**)&P->pcorr, np * kMaxCorr * nk * 8, "per-chunk mean corrections");
+    A((void**)&P->pref, np * nk * 16, "per-chunk mean references");
     A((void**)&P->cmean, np * P->Ns * nk * 16, "chunk means");
   }
   A((void**)&P->scratch, 64, "scratch");
@@ -810,7 +828,7 @@ static int run_pseg(tacaw_plan_t P, const void* frames, int64_t pstride, int64_t
   g.V = P->pseg_V;
   for (int i = 0; i < kMaxCorr; ++i) g.wbin[i] = P->wbin[i];
   g.tw = P->pseg_tw;
-  g.cref = P->cref;
+  g.cref = P->pref;
   g.open = P->pseg_open;
   g.pcorr = P->pcorr;
   g.cmean = P->cmean;
@@ -863,13 +881,15 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
   if (need_ring_write || need_ring_read) TRY(claim_slots(P, probe0, n_probes));
   TRY(ensure_dpart(P, n_probes));
 
-  // 1. references at the first frame of each probe
+  // 1. references: the chunk kernel fixes a kRefSampled reference from the probe's
+  // first chunk; the per-chunk mean sums take the first frame
   if (a == 0) {
-    if (P->strategy == kRefFirstFrame)
-      TRY(hip_check(launch_ref_first_frame(frames, P->d.in_dtype, pstride, P->d.nx, P->rs, probe0,
-                                           n_probes, P->n_k, P->cref, P->st),
+    if (P->pref)
+      TRY(hip_check(launch_ref_sampled(frames, P->d.in_dtype, pstride, fstride, P->d.nx, P->rs,
+                                       first_frame_sample(), probe0, n_probes, P->n_k, P->pref,
+                                       P->st),
                     "reference"));
-    else if (P->strategy == kRefExactMean)
+    if (P->strategy == kRefExactMean)
       TRY(hip_check(launch_ref_mean(frames, P->d.in_dtype, pstride, fstride, P->d.nx, P->rs,
                                     P->n_used, probe0, n_probes, P->n_k, P->cref, P->st),
                     "mean pre-pass"));
@@ -952,11 +972,12 @@ int tacaw_commit_frames(tacaw_plan_t P, int32_t probe0, int32_t n_probes, int64_
   P->ingest_open = false;
   const int64_t a = P->cursor[probe0], b = a + n_frames;
   P->n_timed = 0;
-  if (a == 0 && P->strategy == kRefFirstFrame) {  // reference: frame 0, now in the ring
+  if (a == 0 && P->pref) {  // the per-chunk sums' reference: frame 0, now in the ring
     const int64_t slot0 = probe0 % P->n_slots;
-    TRY(hip_check(launch_ref_first_frame((char*)P->ring + slot0 * P->D * P->n_k * P->esz,
-                                         P->d.in_dtype, P->D * P->n_k, P->d.nx, P->d.nx, probe0,
-                                         n_probes, P->n_k, P->cref, P->st),
+    TRY(hip_check(launch_ref_sampled((char*)P->ring + slot0 * P->D * P->n_k * P->esz,
+                                     P->d.in_dtype, P->D * P->n_k, P->n_k, P->d.nx, P->d.nx,
+                                     first_frame_sample(), probe0, n_probes, P->n_k, P->pref,
+                                     P->st),
                   "reference"));
   }
   if (P->pcorr) {
@@ -1002,7 +1023,7 @@ int tacaw_finalize(tacaw_plan_t P, double* d_S) {
   for (int p = 0; p < P->d.n_probe; ++p)
     if (P->cursor[p] < P->n_used)
       return fail(TACAW_ERR_STATE, "series incomplete for probe " + std::to_string(p));
-  if (P->strategy == kRefFirstFrame) {
+  if (P->strategy == kRefSampled) {
     const CorrArgs c = corr_args(P);
     TRY(hip_check(launch_correct_S(c, P->S, nullptr, 0.0, P->st), "mean correction"));
     if (P->d.n_det > 0)
@@ -1071,7 +1092,7 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   // the mean term comes from the forward pass's bin sums when the window's DFT
   // lives on bins 0, +-1 (those sums exist); otherwise a second pass applies it.
   // Per-chunk means (compact windows only) are applied inside the kernel.
-  const int n_corr = ((global || per_chunk) && P->strategy == kRefFirstFrame) ? P->n_corr : 0;
+  const int n_corr = ((global || per_chunk) && P->strategy == kRefSampled) ? P->n_corr : 0;
   const int Wb = bwd_tile_pixels(P->L);
   const int n_tiles = (P->n_k + Wb - 1) / Wb;
   const int64_t need = (int64_t)n_probes * P->n_k * 16 + (int64_t)n_tiles * 16;

@@ -200,6 +200,34 @@ def generate_into(spec: SeriesSpec, dst: torch.Tensor, probes=None, frame_chunk=
             dst[i, f0:f1] = generate(spec, [p], (f0, f1), device=dst.device)[0]
 
 
+# ------------------------------------------------------------------ non-stationary series
+
+def perturb(psi, kind: str, amount: float, tau: float = 16.0) -> torch.Tensor:
+    """A copy of a series psi [P, n_frames, ny, nx] with a non-stationary part of the
+    kinds the paper discusses (values formed in float64, rounded to psi's dtype):
+
+    "offset":    frame 0 shifted by ``amount`` (a snapshot taken before the
+                 trajectory settled);
+    "transient": amount * exp(-n / tau) added to frame n (thermalisation, Sec. III.A);
+    "drift":     a centre-of-mass drift: phase ramp exp(2 pi i f(kx) n) with a
+                 Doppler frequency f(kx) = amount * (kx - nx/2) / (nx/2) cycles per
+                 frame, linear in the transverse wave-vector (Sec. III.B).
+    """
+    x = np.asarray(psi.numpy(), dtype=np.complex128).copy()
+    P, NT, ny, nx = x.shape
+    n = np.arange(NT, dtype=np.float64)
+    if kind == "offset":
+        x[:, 0] += amount
+    elif kind == "transient":
+        x += (amount * np.exp(-n / tau))[None, :, None, None]
+    elif kind == "drift":
+        f = amount * (np.arange(nx, dtype=np.float64) - nx // 2) / (nx / 2)
+        x *= np.exp(2j * np.pi * n[:, None] * f[None, :])[None, :, None, :]
+    else:
+        raise ValueError(f"unknown perturbation {kind!r}")
+    return torch.from_numpy(x.astype(np.complex64 if psi.dtype == torch.complex64 else np.complex128))
+
+
 # ------------------------------------------------------------------ masks
 
 def disk_mask(ny, nx, radius, center=None, inner=0.0):

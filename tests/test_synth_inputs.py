@@ -33,3 +33,19 @@ def test_masks_and_weights():
     assert ann[32, 32 + 8] == 1 and ann[32, 32 + 7] == 0 and ann[32, 32 + 23] == 1 and ann[32, 32 + 24] == 0
     a = T.loss_weights(4, 16)
     assert a.shape == (4, 16) and np.all(a[3] <= 0.125)
+
+
+def test_non_stationary_series():
+    spec = T.SeriesSpec(2, 40, 2, 8, seed=5, noise_sigma=0.0, n_terms=0)  # psi == 1
+    psi = T.generate(spec)
+    off = T.perturb(psi, "offset", 0.2)
+    assert off.dtype == psi.dtype
+    assert torch.allclose(off[:, 0], torch.full_like(off[:, 0], 1.2))
+    assert torch.equal(off[:, 1:], psi[:, 1:])
+    tr = T.perturb(psi, "transient", 0.5, tau=4.0)
+    assert abs(float(tr[0, 8, 0, 0].real) - (1.0 + 0.5 * np.exp(-2.0))) < 1e-7
+    dr = T.perturb(psi, "drift", 0.01)
+    # phase advance per frame = 2 pi f(kx), f = 0.01 (kx - 4) / 4; |psi| unchanged
+    assert torch.allclose(dr.abs(), psi.abs())
+    ph = np.angle(dr[0, 1, 0].numpy())
+    assert np.allclose(ph, 2 * np.pi * 0.01 * (np.arange(8) - 4) / 4, atol=1e-6)
