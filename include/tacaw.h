@@ -247,6 +247,25 @@ int tacaw_backward(tacaw_plan_t plan, const void* d_frames, int32_t probe0, int3
                    const double* d_gD, const double* d_gDp, void* d_grad_frames,
                    double* d_grad_wparam);
 
+/* Allocation-free form of tacaw_backward, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). Same arguments, results and errors as tacaw_backward,
+ * whose kernels it runs; their scratch (16 bytes per probe and pixel of the call
+ * plus 16 bytes per pixel tile) comes from a fixed library-owned device array of
+ * TACAW_STATIC_SCRATCH_BYTES per GPU (held until the process ends) instead of
+ * plan memory, and no device memory is allocated or freed. The plan's device
+ * must be current. A call needing more scratch fails with SHAPE (split the
+ * probes over several calls). Every call on one GPU shares that array and
+ * writes each scratch value before reading it: calls that overlap in time on
+ * one GPU (other streams or threads) race and must be serialised by the caller.
+ * Errors: as tacaw_backward, plus SHAPE (scratch limit) and INVALID_ARG (the
+ * plan's device is not current). */
+#define TACAW_STATIC_SCRATCH_BYTES (16 << 20)
+int tacaw_backward_static(tacaw_plan_t plan, const void* d_frames, int32_t probe0,
+                          int32_t n_probes, int64_t probe_stride, int64_t frame_stride,
+                          const double* d_gS, const double* d_gD, const double* d_gDp,
+                          void* d_grad_frames, double* d_grad_wparam);
+
 /* Zero every accumulator and frame cursor so the plan can take a new series of
  * the same shape (buffers are kept). */
 int tacaw_reset(tacaw_plan_t plan);

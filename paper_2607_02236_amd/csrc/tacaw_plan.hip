@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1064,10 +1065,43 @@ int tacaw_detector_spectra(tacaw_plan_t P, const double* d_masks, int32_t n_det,
   return TACAW_OK;
 }
 
-int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n_probes,
-                   int64_t pstride, int64_t fstride, const double* gS, const double* gD,
-                   const double* gDp, void* grad, double* grad_wparam) {
-  g_err.clear();
+}  // extern "C"
+
+// Fixed device scratch of tacaw_backward_static: one copy per GPU, held until the
+// process ends. Host code never passes `scratch` itself to a kernel (in host code
+// it is only a stand-in for the symbol); it uses the per-device address below.
+constexpr int64_t kStaticScratchBytes = TACAW_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's `scratch`, looked up once per device (the device
+// must be current).
+static int static_scratch(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return fail(TACAW_ERR_UNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(TACAW_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TACAW_OK;
+}
+
+// The adjoint, with its scratch (gmean [n_probes][n_k] double2, then the tile
+// partials [n_tiles][2] double) either grown in the plan (fixed == nullptr) or
+// taken from `fixed` of fixed_bytes (nothing allocated).
+static int backward_impl(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n_probes,
+                         int64_t pstride, int64_t fstride, const double* gS, const double* gD,
+                         const double* gDp, void* grad, double* grad_wparam, void* fixed,
+                         int64_t fixed_bytes) {
   if (!P) return fail(TACAW_ERR_INVALID_ARG, "plan is NULL");
   if (P->state != 1) return fail(TACAW_ERR_STATE, "plan is not finalized");
   if (!frames || !grad) return fail(TACAW_ERR_INVALID_ARG, "frames and grad must be given");
@@ -1096,11 +1130,19 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   const int Wb = bwd_tile_pixels(P->L);
   const int n_tiles = (P->n_k + Wb - 1) / Wb;
   const int64_t need = (int64_t)n_probes * P->n_k * 16 + (int64_t)n_tiles * 16;
-  if (need > P->scratch_bytes) {
+  double* work = P->scratch;
+  if (fixed) {
+    if (need > fixed_bytes)
+      return fail(TACAW_ERR_SHAPE, "the adjoint needs " + std::to_string(need) +
+                                       " bytes of scratch, more than the fixed " +
+                                       std::to_string(fixed_bytes) + " (16 n_probes n_k + 16 tiles)");
+    work = (double*)fixed;
+  } else if (need > P->scratch_bytes) {
     P->release((void**)&P->scratch);
     P->scratch_bytes = 0;
     TRY(P->alloc((void**)&P->scratch, need, "adjoint scratch"));
     P->scratch_bytes = need;
+    work = P->scratch;
   }
   BwdArgs b{};
   b.in = frames;
@@ -1138,8 +1180,9 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
   b.kappa_S = kappa_S(P);
   b.kappa_p = kappa_probe(P);
   b.qfac = P->qfac;
-  b.gmean = (double2*)P->scratch;
-  b.dwpart = P->scratch + (int64_t)n_probes * P->n_k * 2;
+  // (every scratch value the adjoint's kernels read is written earlier in the same call)
+  b.gmean = (double2*)work;
+  b.dwpart = work + (int64_t)n_probes * P->n_k * 2;
   TRY(hip_check(launch_bwd(P->L, P->d.in_dtype, b, n_tiles, P->st), "adjoint kernel"));
   if (global && n_corr == 0)
     TRY(hip_check(launch_bwd_mean_fix(b, P->d.in_dtype, P->st), "adjoint mean term"));
@@ -1152,6 +1195,33 @@ int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n
                   "window-parameter gradient"));
   }
   return TACAW_OK;
+}
+
+extern "C" {
+
+int tacaw_backward(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n_probes,
+                   int64_t pstride, int64_t fstride, const double* gS, const double* gD,
+                   const double* gDp, void* grad, double* grad_wparam) {
+  g_err.clear();
+  return backward_impl(P, frames, probe0, n_probes, pstride, fstride, gS, gD, gDp, grad,
+                       grad_wparam, nullptr, 0);
+}
+
+int tacaw_backward_static(tacaw_plan_t P, const void* frames, int32_t probe0, int32_t n_probes,
+                          int64_t pstride, int64_t fstride, const double* gS, const double* gD,
+                          const double* gDp, void* grad, double* grad_wparam) {
+  g_err.clear();
+  if (!P) return fail(TACAW_ERR_INVALID_ARG, "plan is NULL");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(TACAW_ERR_HIP, "no current HIP device");
+  }
+  if (dev != P->device) return fail(TACAW_ERR_INVALID_ARG, "the plan's device must be current");
+  void* fixed = nullptr;
+  TRY(static_scratch(dev, &fixed));
+  return backward_impl(P, frames, probe0, n_probes, pstride, fstride, gS, gD, gDp, grad,
+                       grad_wparam, fixed, kStaticScratchBytes);
 }
 
 }  // extern "C"

@@ -70,6 +70,8 @@ def _load():
         "tacaw_finalize": (C.c_int, [P, P]),
         "tacaw_detector_spectra": (C.c_int, [P, P, C.c_int32, P, P]),
         "tacaw_backward": (C.c_int, [P, P, C.c_int32, C.c_int32, C.c_int64, C.c_int64, P, P, P, P, P]),
+        "tacaw_backward_static": (C.c_int, [P, P, C.c_int32, C.c_int32, C.c_int64, C.c_int64, P, P,
+                                            P, P, P]),
         "tacaw_ingest_frames": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int64, C.POINTER(P),
                                           C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
         "tacaw_commit_frames": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int64]),
@@ -92,7 +94,8 @@ def _load():
 lib = _load()
 EXPORTED = ("tacaw_plan", "tacaw_plan_check", "tacaw_push_frames", "tacaw_ingest_frames",
             "tacaw_commit_frames", "tacaw_finalize",
-            "tacaw_detector_spectra", "tacaw_backward", "tacaw_reset", "tacaw_set_stream",
+            "tacaw_detector_spectra", "tacaw_backward", "tacaw_backward_static", "tacaw_reset",
+            "tacaw_set_stream",
             "tacaw_plan_get_info", "tacaw_destroy", "tacaw_last_error", "tacaw_version",
             "tacaw_read_probe", "tacaw_read_probe_columns")
 
@@ -275,8 +278,11 @@ class Plan:
                                           C.c_void_p(Dp.data_ptr() if Dp is not None else None)))
         return (D, Dp) if per_probe else D
 
-    def backward(self, frames, probe0=0, gS=None, gD=None, gDp=None, grad=None, grad_wparam=None):
-        """Adjoint: returns (grad_frames, dLoss/dwindow_param tensor of shape [1])."""
+    def backward(self, frames, probe0=0, gS=None, gD=None, gDp=None, grad=None, grad_wparam=None,
+                 static_scratch=False):
+        """Adjoint: returns (grad_frames, dLoss/dwindow_param tensor of shape [1]).
+        static_scratch: call tacaw_backward_static (the library's fixed scratch, no
+        device allocation in the call)."""
         frames, ps, fs = self._frames_args(frames)
         if frames.shape[1] < self.info()["frames_used"]:
             raise ValueError("backward needs every frame that enters a chunk (frames_used)")
@@ -294,9 +300,10 @@ class Plan:
             return C.c_void_p(t.data_ptr() if t is not None else None)
 
         ins = [None if t is None else t.to(torch.float64).contiguous() for t in (gS, gD, gDp)]
-        _check(lib.tacaw_backward(self.handle, C.c_void_p(frames.data_ptr()), int(probe0),
-                                  int(frames.shape[0]), int(ps), int(fs), ptr(ins[0]), ptr(ins[1]),
-                                  ptr(ins[2]), C.c_void_p(grad.data_ptr()), ptr(grad_wparam)))
+        fn = lib.tacaw_backward_static if static_scratch else lib.tacaw_backward
+        _check(fn(self.handle, C.c_void_p(frames.data_ptr()), int(probe0), int(frames.shape[0]),
+                  int(ps), int(fs), ptr(ins[0]), ptr(ins[1]), ptr(ins[2]),
+                  C.c_void_p(grad.data_ptr()), ptr(grad_wparam)))
         self._keep = ins
         return grad, grad_wparam
 
