@@ -41,12 +41,11 @@ class TacawSpectra(torch.autograd.Function):
         (frames,) = ctx.saved_tensors
         if frames.dim() == 3:
             frames = frames[None]
-        plan = ctx.plan
-        grad, gw = plan.backward(frames.detach().contiguous(), gS=gS,
-                                 gD=gD if ctx.has_masks else None,
-                                 gDp=gDp if ctx.has_masks else None)
-        plan.close()
-        ctx.plan = None
+        # the plan stays open while the graph holds ctx (a second backward with
+        # retain_graph=True reuses it); it is closed when ctx is freed
+        grad, gw = ctx.plan.backward(frames.detach().contiguous(), gS=gS,
+                                     gD=gD if ctx.has_masks else None,
+                                     gDp=gDp if ctx.has_masks else None)
         return grad, gw.reshape(()), None, None, None, None, None, None, None, None, None
 
 

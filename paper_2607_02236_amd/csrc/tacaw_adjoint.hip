@@ -69,8 +69,9 @@ __device__ __forceinline__ float2 rot_g(float2 x, int e) {
 }
 
 // DW: the window-parameter derivative is wanted (dwin_t set). It needs the
-// centred samples again after both transforms; they are re-read then rather
-// than kept in registers through the transforms.
+// centred samples again after both transforms: for complex64 input with
+// L <= 512 they stay in registers through the transforms (KEEP_Z); otherwise
+// (complex128, L = 1024) they are re-read from memory at the end of the chunk.
 // MT: mean term. 0: none (no mean subtracted); 1: accumulate its sum for the
 // separate pass; 2: from the forward pass's bin sums, subtracted at the stores;
 // 3: per-chunk means (chunk s subtracts its own mean mu_s, from the forward

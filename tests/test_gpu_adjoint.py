@@ -33,6 +33,10 @@ def ag():
     (64, 32, 200, 5, 7, 2, "global", "hann_width", 1.1, "c64"),       # mean term in a second pass
     (256, 256, 700, 6, 10, 2, "global", "rect", 1.0, "c64"),          # window DFT on bin 0 only
     (128, 64, 400, 7, 9, 2, "global", "hann", 1.0, "c128"),
+    (256, 128, 700, 6, 10, 2, "global", "tukey", 0.1, "c64"),         # Sec. III.A's Tukey(0.1)
+    (256, 256, 768, 6, 10, 2, "none", "tukey", 0.5, "c64"),
+    (256, 128, 700, 6, 10, 2, "global", "blackmanharris", 1.0, "c64"),  # App. A, custom window
+    (512, 256, 1280, 4, 8, 2, "global", "kaiser5pi", 1.0, "c64"),     # App. A, custom window
 ])
 def test_adjoint_matches_oracle(ag, L, H, NT, ny, nx, P, mode, window, r, dtype):
     spec = T.SeriesSpec(P, NT, ny, nx, dtype=dtype, seed=40 + L, model="lines", n_terms=8)
@@ -44,12 +48,18 @@ def test_adjoint_matches_oracle(ag, L, H, NT, ny, nx, P, mode, window, r, dtype)
     gS = np.random.default_rng(6).random((L, ny * nx)) * 0.1
     x = psi.cuda().requires_grad_(True)
     wp = torch.tensor(r, dtype=torch.float64, device="cuda", requires_grad=True)
-    S, D, Dp = ag.spectra(x, L, H, masks=torch.from_numpy(masks), window=window, window_param=wp,
-                          mean_mode=mode)
+    custom = window in ("blackmanharris", "kaiser5pi")
+    if custom:  # App. A's windows, periodic, from scipy; passed as values
+        import scipy.signal as ss
+
+        spec_w = ("kaiser", 5 * np.pi) if window == "kaiser5pi" else window
+        w_vals = ss.get_window(spec_w, L)
+    S, D, Dp = ag.spectra(x, L, H, masks=torch.from_numpy(masks),
+                          window=w_vals if custom else window, window_param=wp, mean_mode=mode)
     loss = (D * torch.from_numpy(a).cuda()).sum() + (Dp * torch.from_numpy(b).cuda()).sum() \
         + (S.reshape(L, -1) * torch.from_numpy(gS).cuda()).sum()
     loss.backward()
-    w = O.window(window, L, r)
+    w = w_vals if custom else O.window(window, L, r)
     dw = O.window_width_derivative(L, r) if window == "hann_width" else None
     Mf = masks.reshape(4, -1)
     gS_tot = gS + np.einsum("jm,jk->mk", a, Mf)
@@ -95,3 +105,18 @@ def test_adjoint_directional_finite_differences(ag):
     h = 1e-3
     fd = (loss_of(psi, 1 + h) - loss_of(psi, 1 - h)) / (2 * h)
     assert float(wp.grad) == pytest.approx(fd, rel=5e-3)
+
+
+def test_second_backward_with_retained_graph(ag):
+    # the plan stays with the graph: a second backward adds the same gradient again
+    L, H, NT, ny, nx, P = 128, 64, 400, 6, 8, 2
+    spec = T.SeriesSpec(P, NT, ny, nx, dtype="c64", seed=81, model="lines", n_terms=8)
+    x = T.generate(spec).cuda().requires_grad_(True)
+    masks = torch.from_numpy(T.standard_masks(ny, nx, scale=ny / 128))
+    a = torch.from_numpy(T.loss_weights(4, L, seed=4)).cuda()
+    _, D, _ = ag.spectra(x, L, H, masks=masks)
+    loss = (D * a).sum()
+    loss.backward(retain_graph=True)
+    g1 = x.grad.clone()
+    loss.backward()
+    assert torch.allclose(x.grad, 2 * g1, rtol=1e-6, atol=0)

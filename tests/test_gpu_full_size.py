@@ -29,38 +29,70 @@ def resident(spec):
     return psi
 
 
+def one_pixel_per_tile(n_k, tile, seed):
+    """One seeded pixel in every tile of `tile` consecutive pixels."""
+    starts = np.arange(0, n_k, tile)
+    return np.sort(starts + np.random.default_rng(seed).integers(0, tile, size=starts.size))
+
+
 def test_realistic_workload_64_probes_256sq():
-    # 64 probes x 2048 frames x 256 x 256 complex64 (68.7 GB), L = 512, H = 256, 4 masks
+    # 64 probes x 2048 frames x 256 x 256 complex64 (68.7 GB), L = 512, H = 256, 4 masks.
+    # One sampled pixel in every 16-pixel tile of the chunk kernel (4096 tiles); a
+    # second plan with the masks restricted to those pixels gives D and D_p the
+    # oracle can reduce itself.
     from paper_2607_02236_amd import tacaw
 
     spec = T.config_realistic()
     L, H = 512, 256
     psi = resident(spec)
-    masks = torch.from_numpy(T.standard_masks(256, 256)).cuda()
+    masks_np = T.standard_masks(256, 256)
+    masks = torch.from_numpy(masks_np).cuda()
     plan = tacaw.Plan(spec.n_probe, 256, 256, spec.n_frames, L, H, masks=masks)
+    assert plan.info()["tile_pixels"] == 16
+    pix = one_pixel_per_tile(256 * 256, 16, seed=8)
+    ind = np.zeros(256 * 256)
+    ind[pix] = 1.0
+    masks_s = masks_np.reshape(4, -1) * ind[None, :]
+    plan_s = tacaw.Plan(spec.n_probe, 256, 256, spec.n_frames, L, H,
+                        masks=torch.from_numpy(masks_s.reshape(4, 256, 256)).cuda())
     plan.push(psi)
     S = plan.finalize()
     D, Dp = plan.detector_spectra(per_probe=True)
+    plan_s.push(psi)
+    plan_s.finalize()
+    Ds, Dps = plan_s.detector_spectra(per_probe=True)
     # the per-chunk mean on the same resident series
     pseg = tacaw.Plan(spec.n_probe, 256, 256, spec.n_frames, L, H, mean_mode="per_segment")
     pseg.push(psi)
     S_seg = pseg.finalize()
     torch.cuda.synchronize()
     pseg.close()
+    plan_s.close()
     del psi
-    pix = np.sort(np.random.default_rng(8).choice(256 * 256, size=48, replace=False))
+    print(f"sampled {pix.size} pixels, one per tile; regenerating them on the CPU", flush=True)
     sample = T.generate(spec, pixels=pix).numpy()
-    So, _ = O.tacaw_spectra_fft(sample, L, H, O.window("hann", L))
-    Sso, _ = O.tacaw_spectra_fft(sample, L, H, O.window("hann", L), "per_segment")
-    es = rel(S_seg.reshape(L, -1)[:, torch.from_numpy(pix).cuda()].cpu().numpy(), Sso)
+    w = O.window("hann", L)
+    So, Spo = O.tacaw_spectra_fft(sample, L, H, w)
+    Sso, _ = O.tacaw_spectra_fft(sample, L, H, w, "per_segment")
+    del sample
+    pix_t = torch.from_numpy(pix).cuda()
+    es = rel(S_seg.reshape(L, -1)[:, pix_t].cpu().numpy(), Sso)
     print(f"64 probes 256^2, per-chunk mean: S(sampled) {es:.2e}", flush=True)
     assert es <= 1e-5
-    e = rel(S.reshape(L, -1)[:, torch.from_numpy(pix).cuda()].cpu().numpy(), So)
+    e = rel(S.reshape(L, -1)[:, pix_t].cpu().numpy(), So)
     Dref = torch.einsum("jk,mk->jm", masks.reshape(4, -1), S.reshape(L, -1))
     eD = max(rel(D[j].cpu(), Dref[j].cpu()) for j in range(4))
     eDp = rel(Dp.mean(dim=1).cpu(), D.cpu())
     print(f"64 probes 256^2: S(sampled) {e:.2e} D {eD:.2e} mean(Dp) {eDp:.2e}", flush=True)
     assert e <= 1e-5 and eD <= 1e-12 and eDp <= 1e-12
+    # detector spectra of the sampled pixels against the oracle's reduction
+    Mo = masks_s[:, pix]
+    Do = O.detector_spectra(So, Mo)
+    Dpo = np.transpose(O.detector_spectra(Spo, Mo), (1, 0, 2))
+    eDs = max(rel(Ds[j].cpu().numpy(), Do[j]) for j in range(4))
+    eDps = max(rel(Dps[j].cpu().numpy(), Dpo[j]) for j in range(4))
+    print(f"sampled-pixel masks: D {eDs:.2e} D_p {eDps:.2e}", flush=True)
+    assert eDs <= 1e-5 and eDps <= 1e-5
     plan.close()
 
 

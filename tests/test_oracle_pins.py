@@ -86,6 +86,17 @@ def test_tukey_limits_and_scipy(L):
 
 
 @pytest.mark.parametrize("L", [16, 512])
+def test_hann_width_window_is_a_shorter_hann(L):
+    # width r < 1: a periodic Hann of length r L centred on L/2, zero elsewhere
+    # (scipy's periodic Hann is an independent definition of that shape)
+    for r in (0.5, 0.25):
+        M = int(r * L)
+        want = np.zeros(L)
+        want[L // 2 - M // 2:L // 2 + M // 2] = scipy.signal.get_window("hann", M)
+        np.testing.assert_allclose(O.window("hann_width", L, r), want, atol=1e-15)
+
+
+@pytest.mark.parametrize("L", [16, 512])
 def test_hann_width_window(L):
     np.testing.assert_allclose(O.window("hann_width", L, 1.0), O.window("hann", L), atol=1e-15)
     for r in (0.7, 1.0, 1.3):
