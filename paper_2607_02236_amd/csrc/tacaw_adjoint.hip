@@ -58,6 +58,13 @@ template <>
 struct BwdShape<1024> {
   static constexpr int N1 = 16, W = 8;
 };
+// L = 200 (the paper's chunk length): the forward's 10 x 20 split (prime-factor
+// 10-point DFTs); 32 pixels so that every wave holds two bin roles of one fold
+// half (the fold half is then uniform per wave)
+template <>
+struct BwdShape<200> {
+  static constexpr int N1 = 10, W = 32;
+};
 
 // x exp(-2 pi i e / G), G in {2, 4}
 template <int G>
@@ -419,7 +426,16 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
   red[tid] = kvalid ? dA : 0.0;
   red[NT + tid] = kvalid ? dLval : 0.0;
   __syncthreads();
-  for (int w = NT / 2; w > 0; w >>= 1) {
+  // fold onto the largest power of two P2 <= NT (NT = 640 at L = 200), then halve
+  constexpr int P2 = (NT & (NT - 1)) == 0 ? NT : 1 << (31 - __builtin_clz(NT));
+  if constexpr (P2 != NT) {
+    if (tid < NT - P2) {
+      red[tid] += red[tid + P2];
+      red[NT + tid] += red[NT + tid + P2];
+    }
+    __syncthreads();
+  }
+  for (int w = P2 / 2; w > 0; w >>= 1) {
     if (tid < w) {
       red[tid] += red[tid + w];
       red[NT + tid] += red[NT + tid + w];
@@ -507,6 +523,7 @@ int bwd_tile_pixels(int L) {
     case 256: return BwdShape<256>::W;
     case 512: return BwdShape<512>::W;
     case 1024: return BwdShape<1024>::W;
+    case 200: return BwdShape<200>::W;
   }
   return 0;
 }
@@ -520,6 +537,7 @@ int bwd_pass1_size(int L) {
     case 256: return BwdShape<256>::N1;
     case 512: return BwdShape<512>::N1;
     case 1024: return BwdShape<1024>::N1;
+    case 200: return BwdShape<200>::N1;
   }
   return 0;
 }
@@ -531,6 +549,7 @@ hipError_t launch_bwd(int L, int in_dtype, const BwdArgs& a, int n_tiles, hipStr
     case 256: return launch_bl<256>(in_dtype, a, n_tiles, st);
     case 512: return launch_bl<512>(in_dtype, a, n_tiles, st);
     case 1024: return launch_bl<1024>(in_dtype, a, n_tiles, st);
+    case 200: return launch_bl<200>(in_dtype, a, n_tiles, st);
   }
   return hipErrorInvalidValue;
 }

@@ -1116,7 +1116,8 @@ static int backward_impl(tacaw_plan_t P, const void* frames, int32_t probe0, int
     return fail(TACAW_ERR_UNSUPPORTED, "frame_stride too large for 31-bit row-group offsets");
   if (P->H != P->L && 2 * P->H != P->L)
     return fail(TACAW_ERR_UNSUPPORTED, "backward supports hop = L or hop = L/2");
-  if (!is_pow2(P->L)) return fail(TACAW_ERR_UNSUPPORTED, "backward needs a power-of-two seg_len");
+  if (bwd_tile_pixels(P->L) == 0)
+    return fail(TACAW_ERR_UNSUPPORTED, "backward supports seg_len 64 ... 1024 (powers of two) and 200");
   if ((gD || gDp) && P->d.n_det == 0)
     return fail(TACAW_ERR_INVALID_ARG, "detector gradients need plan masks");
   if (bwd_pass1_size(P->L) != P->N1)

@@ -37,6 +37,11 @@ def ag():
     (256, 256, 768, 6, 10, 2, "none", "tukey", 0.5, "c64"),
     (256, 128, 700, 6, 10, 2, "global", "blackmanharris", 1.0, "c64"),  # App. A, custom window
     (512, 256, 1280, 4, 8, 2, "global", "kaiser5pi", 1.0, "c64"),     # App. A, custom window
+    (200, 100, 1000, 6, 10, 2, "global", "hann", 1.0, "c64"),         # the paper's L = 200 (10 x 20)
+    (200, 100, 1000, 6, 10, 2, "global", "hann_width", 1.0, "c64"),
+    (200, 200, 800, 5, 7, 2, "global", "hann_width", 1.1, "c64"),     # mean term in a second pass
+    (200, 100, 900, 5, 7, 2, "per_segment", "hann", 1.0, "c64"),
+    (200, 100, 700, 4, 9, 2, "global", "hann", 1.0, "c128"),
 ])
 def test_adjoint_matches_oracle(ag, L, H, NT, ny, nx, P, mode, window, r, dtype):
     spec = T.SeriesSpec(P, NT, ny, nx, dtype=dtype, seed=40 + L, model="lines", n_terms=8)
