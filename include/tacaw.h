@@ -204,6 +204,18 @@ int tacaw_push_frames(tacaw_plan_t plan, const void* d_frames, int32_t probe0, i
 int tacaw_ingest_frames(tacaw_plan_t plan, int32_t probe0, int32_t n_probes, int64_t n_frames,
                         void** d_dst, int64_t* probe_stride, int64_t* frame_stride);
 
+/* Zero-copy ingest for plans whose ring is stored per pixel tile
+ * (TACAW_FLAG_TILED_RING): as tacaw_ingest_frames, but element (i, n, k) goes to
+ * *d_dst + i * (*probe_stride) + (k / T) * (*tile_stride) + n * (*frame_stride)
+ * + k mod T, with T = *tile_pixels (elements of in_dtype): each tile of T
+ * adjacent pixels holds its frames contiguously. Conditions and errors as
+ * tacaw_ingest_frames (STATE also for a plan without the tiled ring, and for
+ * the per-chunk mean, whose FP64 pass reads per-frame rows); commit with
+ * tacaw_commit_frames. */
+int tacaw_ingest_frames_tiled(tacaw_plan_t plan, int32_t probe0, int32_t n_probes,
+                              int64_t n_frames, void** d_dst, int64_t* probe_stride,
+                              int64_t* frame_stride, int64_t* tile_stride, int32_t* tile_pixels);
+
 /* Mark the frames handed out by the open tacaw_ingest_frames as written: at the
  * end of a series, its remaining chunks run. Errors: STATE (no matching ingest), HIP. */
 int tacaw_commit_frames(tacaw_plan_t plan, int32_t probe0, int32_t n_probes, int64_t n_frames);
@@ -284,6 +296,51 @@ const char* tacaw_last_error(void);
 
 /* Library version string. */
 const char* tacaw_version(void);
+
+/* ---- fused producer (synthetic exit waves) ------------------------------ */
+/* Synthetic exit-wave series written straight into a ring (through the ingest
+ * calls above) or any strided complex64 buffer, standing in for the multislice
+ * producer whose frames the paper reduces as they are produced (Sec. II.B). Per
+ * probe p, frame n and pixel k:
+ *   psi = elastic + sum_{j < n_terms} amplitude (x_j(n) + i y_j(n))
+ *         + noise_sigma (g_r + i g_i),
+ * term j a tone of quantised frequency f_j (2^20 phase steps per cycle, energy
+ * from one of the probe's n_lines Lorentzian lines with centres uniform in
+ * [line_lo_mev, line_hi_mev] and half widths in [hwhm_lo_mev, hwhm_hi_mev], or
+ * uniform in [e_lo_mev, e_hi_mev] when n_lines = 0; dt_fs the frame step),
+ * advanced frame by frame by a float32 rotation that restarts from the
+ * tabulated phase every 64 frames. All random draws come from Philox4x32-10
+ * (Salmon et al., SC 2011) keyed by seed and counted by (probe, pixel or
+ * frame, term), so any frame range can be produced in any order. The tables
+ * are caller-owned device arrays: d_cos, d_sin = cos, sin (2 pi q / 2^20),
+ * q < 2^20 (float32); d_normal = 2^16 standard normals (float32); d_tan =
+ * tan(pi (u - 1/2)), u = (i + 1/2) / 2^16 (float64). */
+typedef struct {
+  int32_t ny, nx;
+  int32_t n_terms;  /* 0 .. 16 */
+  int32_t n_lines;  /* 0: uniform energy band */
+  uint32_t seed;
+  int32_t reserved;
+  double amplitude, noise_sigma, elastic_re, elastic_im;
+  double e_lo_mev, e_hi_mev, line_lo_mev, line_hi_mev, hwhm_lo_mev, hwhm_hi_mev;
+  double dt_fs;
+  const float* d_cos;
+  const float* d_sin;
+  const float* d_normal;
+  const double* d_tan;
+} tacaw_synth_desc;
+
+/* Frames [frame0, frame0 + n_frames) of probes [probe0, probe0 + n_probes) as
+ * complex64: element (i, n, k) at d_dst + i * probe_stride + (k / tile_pixels)
+ * * tile_stride + n * frame_stride + k mod tile_pixels (elements; tile_pixels >=
+ * ny * nx means a plain frame layout, tile_stride then ignored), i.e. the
+ * layouts tacaw_ingest_frames and tacaw_ingest_frames_tiled hand out. One
+ * kernel on hip_stream; nothing is allocated. Errors: INVALID_ARG (null
+ * pointers, tables, strides, alignment), SHAPE (ranges), HIP. */
+int tacaw_synth_frames(const tacaw_synth_desc* desc, void* d_dst, int32_t probe0,
+                       int32_t n_probes, int64_t frame0, int64_t n_frames, int64_t probe_stride,
+                       int64_t frame_stride, int64_t tile_stride, int32_t tile_pixels,
+                       void* hip_stream);
 
 /* Measured HBM read ceiling (measurement support, not a step of the method):
  * reads every byte of the device buffer d_buf once with 16-byte vector loads

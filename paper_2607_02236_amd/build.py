@@ -34,9 +34,15 @@ FLAGS = [
 ]
 
 
+# sources whose floating-point results must be bit-reproducible on the CPU (each
+# product and sum rounded on its own: no fused multiply-add contraction)
+NO_CONTRACT = {"tacaw_producer.hip"}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    extra = ["-ffp-contract=off"] if os.path.basename(src) in NO_CONTRACT else []
+    cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -10,6 +10,11 @@ namespace tacaw {
 constexpr int kMaxDet = 8;   // detector masks per plan
 constexpr int kMaxCorr = 3;  // bins where the window's DFT is non-zero (Hann: 0, 1, L-1)
 
+// Thread-local error message of the C ABI (tacaw_last_error): set_error stores
+// msg and returns code; clear_error empties it.
+int set_error(int code, const char* msg);
+void clear_error();
+
 // Element offset of pixel k inside one input frame whose ny rows of nx pixels are
 // rs elements apart (rs = nx: contiguous; rs > nx: a k-space window of a wider grid).
 __host__ __device__ __forceinline__ int64_t pix_off(int64_t k, int32_t nx, int64_t rs) {

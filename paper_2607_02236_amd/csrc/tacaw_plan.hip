@@ -152,6 +152,10 @@ std::vector<uint16_t> make_dft_matrix(const std::vector<double>& w, bool fp16, i
 
 }  // namespace
 
+// error state shared with the other translation units of the library
+int tacaw::set_error(int code, const char* msg) { return fail(code, msg); }
+void tacaw::clear_error() { g_err.clear(); }
+
 struct tacaw_plan_s {
   tacaw_plan_desc d{};
   hipStream_t st = nullptr;
@@ -927,15 +931,17 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
   return TACAW_OK;
 }
 
-int tacaw_ingest_frames(tacaw_plan_t P, int32_t probe0, int32_t n_probes, int64_t n_frames,
-                        void** d_dst, int64_t* probe_stride, int64_t* frame_stride) {
-  g_err.clear();
-  if (!P || !d_dst || !probe_stride || !frame_stride)
-    return fail(TACAW_ERR_INVALID_ARG, "plan and output pointers must not be NULL");
-  *d_dst = nullptr;
+// Ring rows for the next n_frames frames of probes [probe0, probe0 + n_probes)
+// (deferred mode); chunks that would be overwritten run first.
+static int ingest_rows(tacaw_plan_t P, int32_t probe0, int32_t n_probes, int64_t n_frames,
+                       bool tiled, int64_t* slot0, int64_t* row0) {
   if (P->state != 0) return fail(TACAW_ERR_STATE, "plan is finalized");
   if (!P->deferred) return fail(TACAW_ERR_STATE, "ingest needs the deferred ring mode");
-  if (P->tiled) return fail(TACAW_ERR_STATE, "ingest needs the per-frame ring layout (no TACAW_FLAG_TILED_RING)");
+  if (P->tiled != tiled)
+    return fail(TACAW_ERR_STATE, tiled ? "tiled ingest needs TACAW_FLAG_TILED_RING"
+                                       : "ingest needs the per-frame ring layout (no TACAW_FLAG_TILED_RING)");
+  if (tiled && P->pcorr)
+    return fail(TACAW_ERR_STATE, "the per-chunk mean reads per-frame rows: no tiled ingest");
   if (P->ingest_open) return fail(TACAW_ERR_STATE, "the previous ingest is not committed");
   if (n_probes < 1 || probe0 < 0 || probe0 + (int64_t)n_probes > P->d.n_probe)
     return fail(TACAW_ERR_SHAPE, "probe range outside the plan");
@@ -953,14 +959,44 @@ int tacaw_ingest_frames(tacaw_plan_t P, int32_t probe0, int32_t n_probes, int64_
   TRY(claim_slots(P, probe0, n_probes));
   TRY(ensure_dpart(P, n_probes));
   TRY(deferred_make_room(P, probe0, n_probes, a, b));
-  const int64_t slot0 = probe0 % P->n_slots;
-  *d_dst = (char*)P->ring + ((slot0 * P->D + a % P->D) * P->n_k) * P->esz;
-  *probe_stride = P->D * P->n_k;
-  *frame_stride = P->n_k;
+  *slot0 = probe0 % P->n_slots;
+  *row0 = a % P->D;
   P->ingest_open = true;
   P->ingest_p0 = probe0;
   P->ingest_np = n_probes;
   P->ingest_nf = n_frames;
+  return TACAW_OK;
+}
+
+int tacaw_ingest_frames(tacaw_plan_t P, int32_t probe0, int32_t n_probes, int64_t n_frames,
+                        void** d_dst, int64_t* probe_stride, int64_t* frame_stride) {
+  g_err.clear();
+  if (!P || !d_dst || !probe_stride || !frame_stride)
+    return fail(TACAW_ERR_INVALID_ARG, "plan and output pointers must not be NULL");
+  *d_dst = nullptr;
+  int64_t slot0 = 0, row0 = 0;
+  TRY(ingest_rows(P, probe0, n_probes, n_frames, false, &slot0, &row0));
+  *d_dst = (char*)P->ring + ((slot0 * P->D + row0) * P->n_k) * P->esz;
+  *probe_stride = P->D * P->n_k;
+  *frame_stride = P->n_k;
+  return TACAW_OK;
+}
+
+int tacaw_ingest_frames_tiled(tacaw_plan_t P, int32_t probe0, int32_t n_probes,
+                              int64_t n_frames, void** d_dst, int64_t* probe_stride,
+                              int64_t* frame_stride, int64_t* tile_stride, int32_t* tile_pixels) {
+  g_err.clear();
+  if (!P || !d_dst || !probe_stride || !frame_stride || !tile_stride || !tile_pixels)
+    return fail(TACAW_ERR_INVALID_ARG, "plan and output pointers must not be NULL");
+  *d_dst = nullptr;
+  int64_t slot0 = 0, row0 = 0;
+  TRY(ingest_rows(P, probe0, n_probes, n_frames, true, &slot0, &row0));
+  // ring [slot][tile][row][W]
+  *d_dst = (char*)P->ring + (((slot0 * P->n_tiles) * P->D + row0) * P->W) * P->esz;
+  *probe_stride = (int64_t)P->n_tiles * P->D * P->W;
+  *tile_stride = P->D * P->W;
+  *frame_stride = P->W;
+  *tile_pixels = P->W;
   return TACAW_OK;
 }
 

@@ -58,6 +58,19 @@ class PlanInfo(C.Structure):
     ]
 
 
+class SynthDesc(C.Structure):
+    _fields_ = [
+        ("ny", C.c_int32), ("nx", C.c_int32), ("n_terms", C.c_int32), ("n_lines", C.c_int32),
+        ("seed", C.c_uint32), ("reserved", C.c_int32),
+        ("amplitude", C.c_double), ("noise_sigma", C.c_double),
+        ("elastic_re", C.c_double), ("elastic_im", C.c_double),
+        ("e_lo_mev", C.c_double), ("e_hi_mev", C.c_double),
+        ("line_lo_mev", C.c_double), ("line_hi_mev", C.c_double),
+        ("hwhm_lo_mev", C.c_double), ("hwhm_hi_mev", C.c_double), ("dt_fs", C.c_double),
+        ("d_cos", C.c_void_p), ("d_sin", C.c_void_p), ("d_normal", C.c_void_p), ("d_tan", C.c_void_p),
+    ]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2607_02236_amd.build")
@@ -75,6 +88,11 @@ def _load():
         "tacaw_ingest_frames": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int64, C.POINTER(P),
                                           C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
         "tacaw_commit_frames": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int64]),
+        "tacaw_ingest_frames_tiled": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int64, C.POINTER(P),
+                                                C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                                C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+        "tacaw_synth_frames": (C.c_int, [C.POINTER(SynthDesc), P, C.c_int32, C.c_int32, C.c_int64,
+                                         C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int32, P]),
         "tacaw_reset": (C.c_int, [P]),
         "tacaw_set_stream": (C.c_int, [P, P]),
         "tacaw_plan_get_info": (C.c_int, [P, C.POINTER(PlanInfo)]),
@@ -93,11 +111,11 @@ def _load():
 
 lib = _load()
 EXPORTED = ("tacaw_plan", "tacaw_plan_check", "tacaw_push_frames", "tacaw_ingest_frames",
-            "tacaw_commit_frames", "tacaw_finalize",
+            "tacaw_commit_frames", "tacaw_ingest_frames_tiled", "tacaw_finalize",
             "tacaw_detector_spectra", "tacaw_backward", "tacaw_backward_static", "tacaw_reset",
             "tacaw_set_stream",
             "tacaw_plan_get_info", "tacaw_destroy", "tacaw_last_error", "tacaw_version",
-            "tacaw_read_probe", "tacaw_read_probe_columns")
+            "tacaw_read_probe", "tacaw_read_probe_columns", "tacaw_synth_frames")
 
 
 def _check(rc):
@@ -158,7 +176,8 @@ class Plan:
 
     masks: optional torch float64 CUDA tensor [n_det, ny, nx] (enables the fused
     per-probe detector spectra). ring_frames > seg_len: deferred streaming ring;
-    tiled_ring: store that ring per pixel tile (pushes only, hop = seg_len / 2).
+    tiled_ring: store that ring per pixel tile (hop = seg_len / 2; pushes, or a
+    producer through ingest_tiled).
     """
 
     def __init__(self, n_probe, ny, nx, n_frames, seg_len, hop=None, window="hann",
@@ -171,6 +190,7 @@ class Plan:
         self.n_probe, self.ny, self.nx = int(n_probe), int(ny), int(nx)
         self.seg_len, self.hop, self.n_frames = int(seg_len), int(hop), int(n_frames)
         self.in_dtype = in_dtype
+        self.tiled_ring = bool(tiled_ring)
         self.tdtype = torch.complex64 if in_dtype == "c64" else torch.complex128
         self.masks = None
         n_det, mptr = 0, 0
@@ -244,6 +264,17 @@ class Plan:
                            "<c8" if self.in_dtype == "c64" else "<c16")
         self._ingest = (int(probe0), int(n_probes), int(n_frames))
         return torch.as_tensor(view, device="cuda")
+
+    def ingest_tiled(self, n_frames: int, probe0: int = 0, n_probes: int = 1) -> dict:
+        """Zero-copy ingest into a tiled ring: the layout (pointer and strides in
+        elements) a producer writes the next frames to, then commit()."""
+        ptr, ps, fs, ts, tp = C.c_void_p(), C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib.tacaw_ingest_frames_tiled(self.handle, int(probe0), int(n_probes), int(n_frames),
+                                             C.byref(ptr), C.byref(ps), C.byref(fs), C.byref(ts),
+                                             C.byref(tp)))
+        self._ingest = (int(probe0), int(n_probes), int(n_frames))
+        return {"ptr": ptr.value, "probe_stride": ps.value, "frame_stride": fs.value,
+                "tile_stride": ts.value, "tile_pixels": tp.value}
 
     def commit(self):
         """Mark the frames of the last ingest() as written."""
@@ -378,3 +409,56 @@ def read_probe_columns(buf: torch.Tensor, rows: int, seg_bytes: int = 128,
     _check(lib.tacaw_read_probe_columns(C.c_void_p(buf.data_ptr()), rows, row_bytes, int(seg_bytes),
                                         sptr, C.c_void_p(out.data_ptr())))
     return out
+
+
+class Producer:
+    """The library's fused producer (tacaw_synth_frames): synthetic complex64 exit
+    waves from Philox4x32-10 counters. spec carries the model parameters (a
+    tacaw_synth.philox.ProducerSpec or anything with the same fields); tables are
+    CUDA tensors cos, sin (2^20, float32), normal (2^16, float32), tan (2^16,
+    float64)."""
+
+    def __init__(self, spec, tables: dict, stream=None):
+        self.spec = spec
+        self.tables = {k: v.contiguous() for k, v in tables.items()}
+        self.stream, self._sptr = _stream_ptr(stream)
+        t = self.tables
+        e = complex(spec.elastic)
+        self.desc = SynthDesc(int(spec.ny), int(spec.nx), int(spec.n_terms), int(spec.n_lines),
+                              int(spec.seed) & 0xFFFFFFFF, 0, float(spec.amplitude),
+                              float(spec.noise_sigma), e.real, e.imag, float(spec.e_lo_mev),
+                              float(spec.e_hi_mev), float(spec.line_lo_mev), float(spec.line_hi_mev),
+                              float(spec.hwhm_lo_mev), float(spec.hwhm_hi_mev), float(spec.dt_fs),
+                              t["cos"].data_ptr(), t["sin"].data_ptr(), t["normal"].data_ptr(),
+                              t["tan"].data_ptr())
+
+    def write(self, ptr: int, probe0: int, n_probes: int, frame0: int, n_frames: int,
+              probe_stride: int, frame_stride: int, tile_stride: int = 0, tile_pixels: int = 0):
+        """Frames [frame0, frame0 + n_frames) of probes probe0.. into device memory at ptr
+        (strides in complex64 elements; tile_pixels 0 = plain frames)."""
+        tp = int(tile_pixels) if tile_pixels else int(self.spec.ny * self.spec.nx)
+        _check(lib.tacaw_synth_frames(C.byref(self.desc), C.c_void_p(ptr), int(probe0), int(n_probes),
+                                      int(frame0), int(n_frames), int(probe_stride), int(frame_stride),
+                                      int(tile_stride), tp, self._sptr))
+
+    def into(self, dst: torch.Tensor, probe0: int = 0, frame0: int = 0):
+        """Fill a complex64 CUDA tensor [n_probes, n_frames, ny, nx] (contiguous frames)."""
+        if dst.dtype != torch.complex64 or not dst.is_cuda or dst.stride(3) != 1 \
+                or dst.stride(2) != dst.shape[3]:
+            raise ValueError("dst must be a complex64 CUDA tensor with contiguous frames")
+        self.write(dst.data_ptr(), probe0, dst.shape[0], frame0, dst.shape[1], dst.stride(0),
+                   dst.stride(1))
+        return dst
+
+    def into_ring(self, plan: "Plan", n_frames: int, probe0: int, n_probes: int, frame0: int):
+        """Zero-copy: write the next n_frames frames straight into the plan's (tiled or
+        per-frame) ring and commit them."""
+        if plan.tiled_ring:
+            lay = plan.ingest_tiled(n_frames, probe0, n_probes)
+            self.write(lay["ptr"], probe0, n_probes, frame0, n_frames, lay["probe_stride"],
+                       lay["frame_stride"], lay["tile_stride"], lay["tile_pixels"])
+        else:
+            view = plan.ingest(n_frames, probe0, n_probes)
+            self.write(view.data_ptr(), probe0, n_probes, frame0, n_frames, view.stride(0),
+                       view.stride(1))
+        plan.commit()

@@ -31,6 +31,8 @@ import math
 import numpy as np
 import torch
 
+from . import philox  # noqa: F401  (the fused producer's CPU twin)
+
 PHASE_BITS = 20
 Q = 1 << PHASE_BITS
 NOISE_BITS = 16
