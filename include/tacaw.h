@@ -129,17 +129,18 @@ typedef struct {
 } tacaw_plan_desc;
 
 /* flags: record HIP events around the chunk kernel of every push; the duration
- * of the last push's kernel is reported in tacaw_plan_info.last_chunk_kernel_ms
- * (reading it synchronizes with the plan's stream; -1 if that push completed no
- * chunk). */
+ * of the last push's chunk launches (or of the last ingest and its commit) is
+ * reported in tacaw_plan_info.last_chunk_kernel_ms (reading it synchronizes with
+ * the plan's stream; -1 if that push completed no chunk). */
 #define TACAW_FLAG_TIME_KERNELS 1
 /* flags: deferred ring mode (ring_frames > 0, hop = seg_len/2) with the ring
  * stored per pixel tile of the chunk kernel, [slot][tile][row][tile pixels],
  * instead of per frame: a tile's chunk is then contiguous in memory, so the
  * chunk kernel needs a few address translations per chunk instead of one per
  * frame (large frames, e.g. 1024^2 pixels, otherwise miss the translation
- * caches on most loads). Pushes only: tacaw_ingest_frames needs the per-frame
- * layout and fails with STATE on such a plan. */
+ * caches on most loads). Pushes, or a producer writing through
+ * tacaw_ingest_frames_tiled (tacaw_ingest_frames fails with STATE on such a
+ * plan). */
 #define TACAW_FLAG_TILED_RING 2
 
 typedef struct {
@@ -313,7 +314,7 @@ const char* tacaw_version(void);
  * (Salmon et al., SC 2011) keyed by seed and counted by (probe, pixel or
  * frame, term), so any frame range can be produced in any order. The tables
  * are caller-owned device arrays: d_cos, d_sin = cos, sin (2 pi q / 2^20),
- * q < 2^20 (float32); d_normal = 2^16 standard normals (float32); d_tan =
+ * q < 2^20 (float32); d_normal = 2^12 standard normals (float32); d_tan =
  * tan(pi (u - 1/2)), u = (i + 1/2) / 2^16 (float64). */
 typedef struct {
   int32_t ny, nx;

@@ -958,6 +958,7 @@ static int ingest_rows(tacaw_plan_t P, int32_t probe0, int32_t n_probes, int64_t
     return fail(TACAW_ERR_SHAPE, "ingest probes must occupy consecutive ring slots");
   TRY(claim_slots(P, probe0, n_probes));
   TRY(ensure_dpart(P, n_probes));
+  P->n_timed = 0;  // the chunk launches of this ingest and its commit are timed together
   TRY(deferred_make_room(P, probe0, n_probes, a, b));
   *slot0 = probe0 % P->n_slots;
   *row0 = a % P->D;
@@ -1008,7 +1009,6 @@ int tacaw_commit_frames(tacaw_plan_t P, int32_t probe0, int32_t n_probes, int64_
     return fail(TACAW_ERR_STATE, "commit does not match the open ingest");
   P->ingest_open = false;
   const int64_t a = P->cursor[probe0], b = a + n_frames;
-  P->n_timed = 0;
   if (a == 0 && P->pref) {  // the per-chunk sums' reference: frame 0, now in the ring
     const int64_t slot0 = probe0 % P->n_slots;
     TRY(hip_check(launch_ref_sampled((char*)P->ring + slot0 * P->D * P->n_k * P->esz,

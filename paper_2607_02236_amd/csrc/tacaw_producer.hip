@@ -18,8 +18,8 @@
 // same bits (this file is compiled with -ffp-contract=off, and the kernels
 // say so too). f_j, phi_j: Philox((p, k, j, 0), (seed, 0x21)); line centres and
 // half widths: Philox((p, l, 0, 0), (seed, 0x11)); noise: word n mod 4 of
-// Philox((p, n / 4, k, 0), (seed, 0x41)), its low and high 16 bits indexing a
-// table of standard normals.
+// Philox((p, n / 4, k, 0), (seed, 0x41)), the low 12 bits of its two 16-bit
+// halves indexing a table of 2^12 standard normals.
 #include <stdint.h>
 
 #include "../../include/tacaw.h"
@@ -30,6 +30,7 @@ namespace tacaw {
 constexpr int kQ = 1 << 20;
 constexpr int kBlock = 64;
 constexpr int kMaxTerms = 16;
+constexpr int kNormals = 1 << 12;  // standard normals in the noise table
 constexpr int kMaxLines = 1 << 20;
 
 struct Philox4 {
@@ -87,9 +88,15 @@ __global__ void __launch_bounds__(256) synth_frames_kernel(const SynthArgs a) {
 #pragma clang fp contract(off)
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
+  const tacaw_synth_desc& d = a.d;
+  // the normal table in LDS (two random reads per value would otherwise go to L2)
+  __shared__ float s_normal[kNormals];
+  if (d.noise_sigma != 0.0) {
+    for (int e = threadIdx.x; e < kNormals; e += blockDim.x) s_normal[e] = d.d_normal[e];
+    __syncthreads();
+  }
   if (k >= a.n_k) return;
   const uint32_t p = (uint32_t)(a.probe0 + i);
-  const tacaw_synth_desc& d = a.d;
   // the pixel's terms: rotation per frame and phase step
   float rc[T > 0 ? T : 1], rs[T > 0 ? T : 1];
   uint32_t fq[T > 0 ? T : 1], phq[T > 0 ? T : 1];
@@ -139,8 +146,8 @@ __global__ void __launch_bounds__(256) synth_frames_kernel(const SynthArgs a) {
           nz = philox4x32_10(p, (uint32_t)(n >> 2), (uint32_t)k, 0u, d.seed, 0x41u);
         const int q = (int)(n & 3);
         const uint32_t w = q == 0 ? nz.x[0] : q == 1 ? nz.x[1] : q == 2 ? nz.x[2] : nz.x[3];
-        re = re + d.d_normal[w & 0xFFFFu] * sig;
-        im = im + d.d_normal[w >> 16] * sig;
+        re = re + s_normal[w & (kNormals - 1)] * sig;
+        im = im + s_normal[(w >> 16) & (kNormals - 1)] * sig;
       }
       out[(n - a.frame0) * a.fstride] = make_float2(re, im);
     }

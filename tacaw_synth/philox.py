@@ -21,8 +21,8 @@ block. Every product and sum is one IEEE float32 operation in a fixed order.
 f_j and phi_j come from Philox((p, k, j, 0), (seed, 0x21)); the frequency is
 drawn from the probe's Lorentzian lines (centre and half width from
 Philox((p, l, 0, 0), (seed, 0x11))) or from a uniform band. Noise indices come
-from Philox((p, n >> 2, k, 0), (seed, 0x41)), word n & 3 (low and high 16 bits
-index a table of standard normals).
+from Philox((p, n >> 2, k, 0), (seed, 0x41)), word n & 3 (the low 12 bits of its
+two 16-bit halves index a table of 2^12 standard normals).
 """
 
 from __future__ import annotations
@@ -36,6 +36,7 @@ W0, W1 = 0x9E3779B9, 0xBB67AE85
 MASK32 = np.uint64(0xFFFFFFFF)
 Q = 1 << 20
 BLOCK = 64            # frames between restarts of the rotation recurrence
+NORMALS = 1 << 12     # entries of the noise table
 STREAM_LINES, STREAM_TERMS, STREAM_NOISE = 0x11, 0x21, 0x41
 PLANCK_EV_S = 6.62607015e-34 / 1.602176634e-19
 
@@ -77,6 +78,7 @@ class ProducerSpec:
     hwhm_lo_mev: float = 0.5
     hwhm_hi_mev: float = 3.0
     dt_fs: float = 5.0
+    dtype: str = "c64"
 
     @property
     def n_k(self) -> int:
@@ -91,7 +93,7 @@ _TAB: dict = {}
 
 
 def tables():
-    """cos/sin of 2 pi q / Q (float32, computed in float64), 2^16 standard normals
+    """cos/sin of 2 pi q / Q (float32, computed in float64), 2^12 standard normals
     (float32, PCG64 seed 0x7ACA5) and tan(pi (u - 1/2)) at u = (i + 1/2) / 2^16
     (float64): the producer's inputs, identical on both sides."""
     if not _TAB:
@@ -99,7 +101,7 @@ def tables():
         u = (np.arange(1 << 16, dtype=np.float64) + 0.5) / (1 << 16)
         _TAB.update(
             cos=np.cos(q).astype(np.float32), sin=np.sin(q).astype(np.float32),
-            normal=np.random.Generator(np.random.PCG64(0x7ACA5)).standard_normal(1 << 16)
+            normal=np.random.Generator(np.random.PCG64(0x7ACA5)).standard_normal(NORMALS)
             .astype(np.float32),
             tan=np.tan(np.pi * (u - 0.5)))
     return _TAB
@@ -168,8 +170,8 @@ def generate(spec: ProducerSpec, probes=None, frames=None, pixels=None) -> np.nd
             w = philox4x32_10((p, (n >> np.uint64(2))[:, None], pix.astype(np.uint64)[None, :], 0),
                               (spec.seed, STREAM_NOISE))
             word = np.choose((n & np.uint64(3)).astype(np.int64)[:, None], w)
-            g_r = tab["normal"][(word & np.uint32(0xFFFF)).astype(np.int64)]
-            g_i = tab["normal"][(word >> np.uint32(16)).astype(np.int64)]
+            g_r = tab["normal"][(word & np.uint32(NORMALS - 1)).astype(np.int64)]
+            g_i = tab["normal"][((word >> np.uint32(16)) & np.uint32(NORMALS - 1)).astype(np.int64)]
             re = re.reshape(nb * BLOCK, K) + g_r * sig
             im = im.reshape(nb * BLOCK, K) + g_i * sig
         else:
