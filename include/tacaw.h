@@ -64,8 +64,14 @@ extern "C" {
 
 /* ---- time transform ------------------------------------------------------ */
 #define TACAW_FFT_F32 0     /* radix FFT in FP32, staged in LDS                      */
-#define TACAW_GEMM_BF16X3 1 /* DFT as a GEMM on MFMA, bf16 hi/lo split x3, FP32 acc   */
-#define TACAW_GEMM_F16X3 2  /* DFT as a GEMM on MFMA, scaled fp16 hi/lo split x3     */
+#define TACAW_GEMM_BF16X3 1 /* DFT as a GEMM on MFMA, bf16 hi/lo split x3, FP32 acc;  */
+                            /* L = 128..1024 (powers of two). With a window whose DFT */
+                            /* lives on bins 0 and +-1 it streams like the FFT form   */
+                            /* (pushes of any size, rings, exact mean correction);    */
+                            /* otherwise each probe's series comes in one push        */
+#define TACAW_GEMM_F16X3 2  /* DFT as a GEMM on MFMA, scaled fp16 hi/lo split x3;     */
+                            /* L = 128..1024; each probe's whole series in one push   */
+                            /* (its operand scale and the exact mean are pre-passes)  */
 
 /* ---- input element type -------------------------------------------------- */
 #define TACAW_C64 0  /* complex64: interleaved float (re, im), 8 bytes           */
@@ -114,8 +120,8 @@ typedef struct {
                           /* push) = deferred mode: pushes are copied into the ring  */
                           /* and completed chunks are processed from it in batches,  */
                           /* when the ring would overwrite them and at the end of    */
-                          /* each probe's series (fewer, larger launches; FFT form,  */
-                          /* compact windows)                                        */
+                          /* each probe's series (fewer, larger launches; FFT or     */
+                          /* bf16 GEMM form, compact windows)                        */
   int64_t k_row_stride;   /* k-space window (the k-ROI of Sec. II.B): elements       */
                           /* between the input's pixel rows, >= nx (0 = nx). The    */
                           /* ny x nx pixels reduced are then a window of a wider     */

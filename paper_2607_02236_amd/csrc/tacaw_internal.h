@@ -47,6 +47,7 @@ struct SegArgs {
   int32_t corr_skip;       // leave the correction bins out of S (the per-chunk mean kernel
                            // supplies their whole FP64 value)
   int32_t n_corr;          // 1 (rectangular) or 3 (Hann)
+  int32_t corr_rows[kMaxCorr];  // output rows of the correction bins 0, 1, L-1 (GEMM form)
   const float* win_t;      // window, transposed per thread: [N2][N1] (t = N2*n1 + n2)
   const float2* tw;        // inter-pass twiddles exp(-2 pi i n2 k1 / L): [N2][N1]
   double2* cref;           // [n_probe][n_k] reference subtracted before the window; with

@@ -312,6 +312,7 @@ static int run_chunks(tacaw_plan_t P, const void* src, int64_t pstride, int64_t 
   g.track_mean = P->strategy == kRefSampled ? 1 : 0;
   g.corr_skip = P->pcorr ? 1 : 0;
   g.n_corr = P->n_corr;
+  for (int b = 0; b < kMaxCorr; ++b) g.corr_rows[b] = P->rows[b];
   g.win_t = P->win_t;
   g.tw = P->tw;
   g.cref = P->cref;
@@ -507,8 +508,10 @@ int tacaw_plan_check(const tacaw_plan_desc* d) {
         d->ring_frames >= ((int64_t)1 << 30))
       return fail(TACAW_ERR_INVALID_ARG,
                   "ring_frames must be 0 or a multiple of seg_len/2 in (seg_len, 2^30)");
-    if (d->transform != TACAW_FFT_F32)
-      return fail(TACAW_ERR_UNSUPPORTED, "deferred ring mode needs the FFT transform");
+    if (d->transform == TACAW_GEMM_F16X3)
+      return fail(TACAW_ERR_UNSUPPORTED,
+                  "deferred ring mode needs the FFT or bf16 GEMM transform (fp16 scales its "
+                  "operands from the whole series)");
   }
   if (d->flags & TACAW_FLAG_TILED_RING) {
     if (d->ring_frames == 0)
@@ -593,7 +596,9 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   P->bins[2] = P->L - 1;
   for (int b = 0; b < kMaxCorr; ++b) P->rows[b] = (P->bins[b] + P->roi) % P->L;
   for (int b = 0; b < kMaxCorr; ++b) P->wbin[b] = Wm[P->bins[b]];
-  if (gemm)  // the GEMM form subtracts the exact mean (or zero) before splitting
+  if (gemm && (d->transform == TACAW_GEMM_F16X3 || !P->compact))
+    // fp16 (its operand scale needs the whole series) and non-compact windows: the
+    // exact mean (or zero) is subtracted before splitting
     P->strategy = d->mean_mode == TACAW_MEAN_GLOBAL ? kRefExactMean : kRefZero;
   else if (P->compact)
     P->strategy = kRefSampled;
@@ -864,7 +869,10 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
       return fail(TACAW_ERR_STATE, "probes of one push must be at the same frame cursor");
   const int64_t b = a + n_frames;
   if (b > P->d.n_frames) return fail(TACAW_ERR_SHAPE, "push goes beyond the plan's n_frames");
-  if ((P->strategy == kRefExactMean || transform_is_gemm(P->d.transform)) &&
+  // the exact-mean pre-pass, the fp16 operand scale and the GEMM form without the
+  // streaming reference read each probe's whole series at once
+  if ((P->strategy == kRefExactMean ||
+       (transform_is_gemm(P->d.transform) && P->strategy != kRefSampled)) &&
       (a != 0 || b < P->n_used))
     return fail(TACAW_ERR_UNSUPPORTED,
                 "this plan needs each probe's whole series in one push (exact mean pre-pass)");
@@ -898,7 +906,7 @@ int tacaw_push_frames(tacaw_plan_t P, const void* frames, int32_t probe0, int32_
       TRY(hip_check(launch_ref_mean(frames, P->d.in_dtype, pstride, fstride, P->d.nx, P->rs,
                                     P->n_used, probe0, n_probes, P->n_k, P->cref, P->st),
                     "mean pre-pass"));
-    if (transform_is_gemm(P->d.transform))
+    if (P->d.transform == TACAW_GEMM_F16X3)
       TRY(hip_check(launch_gemm_scale(frames, P->d.in_dtype, pstride, fstride, P->d.nx, P->rs,
                                       P->n_used, probe0, n_probes, P->n_k,
                                       P->d.transform == TACAW_GEMM_F16X3 ? 1 : 0, P->cref,

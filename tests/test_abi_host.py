@@ -58,7 +58,6 @@ def _ok(**over):
     (dict(ny=1 << 16, nx=1 << 16), "INVALID_ARG"),
     (dict(window="custom"), "INVALID_ARG"),
     (dict(temperature_K=-1.0), "INVALID_ARG"),
-    (dict(transform="gemm_f16x3", seg_len=1024, n_frames=2048, hop=512), "UNSUPPORTED"),
     (dict(omega_half=-1), "INVALID_ARG"),
     (dict(k_row_stride=7), "INVALID_ARG"),    # k window: row stride below nx
     (dict(ring_frames=128), "INVALID_ARG"),   # must exceed seg_len
@@ -95,6 +94,8 @@ def test_valid_descriptors_pass():
     tacaw.check_desc(**_ok(mean_mode="per_segment", ring_frames=192, flags=tacaw.FLAG_TILED_RING))
     tacaw.check_desc(**_ok(seg_len=200, hop=100, n_frames=3200, dt_fs=15.0, omega_half=90))
     tacaw.check_desc(**_ok(omega_half=1, transform="gemm_f16x3", temperature_K=50.0))
+    tacaw.check_desc(**_ok(transform="gemm_f16x3", seg_len=1024, n_frames=2048, hop=512))
+    tacaw.check_desc(**_ok(transform="gemm_bf16x3", ring_frames=192, flags=tacaw.FLAG_TILED_RING))
 
 
 def test_null_arguments_are_rejected_without_a_device():

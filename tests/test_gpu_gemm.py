@@ -83,11 +83,71 @@ def test_gemm_multi_probe_multi_chunk(tacaw, form, L, H, NT, ny, nx, P):
     assert e <= BARS[form]
 
 
-def test_gemm_rejects_streaming_and_unsupported_lengths(tacaw):
+@pytest.mark.parametrize("form,roi", [("gemm_bf16x3", 0), ("gemm_f16x3", 0), ("gemm_bf16x3", 100.0)])
+def test_gemm_chunk_length_1024(tacaw, form, roi):
+    # L = 1024: all bins need two row groups of the GEMM; an energy window one
+    from paper_2607_02236_amd import axes
+
+    L, H, NT, ny, nx, P = 1024, 512, 2048, 6, 11, 2
+    spec = T.SeriesSpec(P, NT, ny, nx, dtype="c64", seed=97, model="lines", n_terms=8)
+    psi = T.generate(spec)
+    masks = T.standard_masks(ny, nx, scale=min(ny, nx) / 128)
+    masks[3] = np.random.default_rng(4).random((ny, nx))
+    M = axes.omega_half_for(L, 5.0, e_max_mev=roi) if roi else 0
+    plan = tacaw.Plan(P, ny, nx, NT, L, H, transform=form, masks=torch.from_numpy(masks).cuda(),
+                      omega_half=M)
+    plan.push(psi.cuda())
+    S = plan.finalize().cpu().numpy().reshape(plan.n_omega, -1)
+    D, Dp = plan.detector_spectra(per_probe=True)
+    torch.cuda.synchronize()
+    So, Spo = O.tacaw_spectra(psi.numpy(), L, H, O.window("hann", L))
+    rows = (np.arange(plan.n_omega) - M) % L if M else np.arange(L)
+    So, Spo = So[rows], Spo[:, rows]
+    Do = O.detector_spectra(So, masks)
+    Dpo = np.transpose(O.detector_spectra(Spo, masks), (1, 0, 2))
+    e = max([rel(S, So)] + [rel(D.cpu().numpy()[j], Do[j]) for j in range(4)]
+            + [rel(Dp.cpu().numpy()[j], Dpo[j]) for j in range(4)])
+    print(f"{form} L=1024 window {roi} meV ({plan.n_omega} bins): max rel err {e:.2e}")
+    assert e <= BARS[form]
+    plan.close()
+
+
+@pytest.mark.parametrize("ring,tiled", [(0, False), (2048, False), (2048, True)])
+def test_gemm_bf16_streamed_pushes(tacaw, ring, tiled):
+    # the streaming form: a reference fixed by the first chunk and the exact FP64
+    # mean correction, frames before a push from the ring (immediate, deferred, tiled)
+    L, H, NT, ny, nx, P, piece = 1024, 512, 3072, 5, 13, 2, 256
+    spec = T.SeriesSpec(P, NT, ny, nx, dtype="c64", seed=98, model="lines", n_terms=8)
+    psi = T.generate(spec)
+    masks = T.standard_masks(ny, nx, scale=min(ny, nx) / 128)
+    masks[3] = np.random.default_rng(5).random((ny, nx))
+    plan = tacaw.Plan(P, ny, nx, NT, L, H, transform="gemm_bf16x3",
+                      masks=torch.from_numpy(masks).cuda(), ring_frames=ring, tiled_ring=tiled)
+    x = psi.cuda()
+    for f0 in range(0, NT, piece):
+        plan.push(x[:, f0:f0 + piece])
+    S = plan.finalize().cpu().numpy().reshape(L, -1)
+    D, Dp = plan.detector_spectra(per_probe=True)
+    torch.cuda.synchronize()
+    So, Spo = O.tacaw_spectra(psi.numpy(), L, H, O.window("hann", L))
+    Do = O.detector_spectra(So, masks)
+    Dpo = np.transpose(O.detector_spectra(Spo, masks), (1, 0, 2))
+    e = max([rel(S, So)] + [rel(D.cpu().numpy()[j], Do[j]) for j in range(4)]
+            + [rel(Dp.cpu().numpy()[j], Dpo[j]) for j in range(4)])
+    rows = [0, 1, L - 1]
+    eR = rel(S[rows], So[rows])
+    print(f"bf16x3 streamed (ring {ring}{' tiled' if tiled else ''}): max rel err {e:.2e}, "
+          f"rows 0, +-1 {eR:.2e}")
+    assert e <= BARS["gemm_bf16x3"] and eR <= BARS["gemm_bf16x3"]
+    plan.close()
+
+
+def test_gemm_rejects_streaming_fp16_and_unsupported_lengths(tacaw):
     with pytest.raises(tacaw.TacawError) as e:
-        tacaw.Plan(1, 4, 4, 2048, 1024, 512, transform="gemm_f16x3")
+        tacaw.Plan(1, 4, 4, 400, 200, 100, transform="gemm_bf16x3")
     assert e.value.kind == "UNSUPPORTED"
-    plan = tacaw.Plan(1, 4, 4, 512, 256, 128, transform="gemm_bf16x3")
+    # fp16 scales its operands from the whole series: whole-series pushes only
+    plan = tacaw.Plan(1, 4, 4, 512, 256, 128, transform="gemm_f16x3")
     psi = T.generate(T.SeriesSpec(1, 512, 4, 4)).cuda()
     with pytest.raises(tacaw.TacawError) as e:
         plan.push(psi[:, :300])
