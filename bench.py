@@ -458,9 +458,13 @@ def bench_producer(args, spec, L, H):
     masks = torch.from_numpy(T.standard_masks(spec.ny, spec.nx, scale=spec.ny / 256)).cuda()
     tabs = {k: torch.from_numpy(v).cuda() for k, v in T.philox.tables().items()}
     prod = tacaw.Producer(spec, tabs, stream=stream)
+    from paper_2607_02236_amd import axes
+
+    M = axes.omega_half_for(L, spec.dt_fs, e_max_mev=args.roi_mev) if args.roi_mev > 0 else 0
     plan = tacaw.Plan(P, spec.ny, spec.nx, NT, L, H, masks=masks, time_kernels=True, stream=stream,
                       ring_frames=ring, tiled_ring=args.ring_layout == "tiled",
-                      max_probes_in_flight=batch, mean_mode=args.mean_mode)
+                      max_probes_in_flight=batch, mean_mode=args.mean_mode, transform=args.form,
+                      dt_fs=spec.dt_fs, omega_half=M)
     log(f"plan: {P} probes x {NT} frames x {spec.ny}x{spec.nx}, ring of {ring} frames for "
         f"{batch} probes ({plan.info()['device_bytes'] / 1e9:.1f} GB on the device)")
     n_om = plan.n_omega
@@ -517,8 +521,8 @@ def bench_producer(args, spec, L, H):
     achieved = b_alg / (k_ms * 1e-3) / 1e9
     csrc = os.path.join(ROOT, "paper_2607_02236_amd", "csrc")
     run_cfg = dict(probes=P, frames=NT, ny=spec.ny, nx=spec.nx, seg_len=L, hop=H, dtype="c64",
-                   form="fft", mean_mode=args.mean_mode, streaming=True, gradient=False,
-                   omega_half=0, producer=True)
+                   form=args.form, mean_mode=args.mean_mode, streaming=True, gradient=False,
+                   omega_half=int(M), producer=True)
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -536,7 +540,9 @@ def bench_producer(args, spec, L, H):
         "config": {
             "workload": f"{P} probes x {NT} frames x {spec.ny}x{spec.nx} c64, Welch L={L} H={H} "
                         f"periodic Hann, {args.mean_mode.replace('_', '-')} mean, "
-                        f"{masks.shape[0]} detector masks, transform fft, frames written by the "
+                        f"{masks.shape[0]} detector masks, transform {args.form}"
+                        + (f", energy window |E| <= {args.roi_mev:g} meV ({n_om} bins)" if M else "")
+                        + ", frames written by the "
                         f"fused producer in pieces of {piece} straight into a {args.ring_layout} "
                         f"ring of {ring} frames ({batch} probes in flight); the step includes "
                         "the producer",
@@ -554,6 +560,20 @@ def bench_producer(args, spec, L, H):
                     "all its launches (HIP events on the plan's stream)",
         },
     }
+    if args.form != "fft":
+        n_seg = (NT - L) // H + 1
+        m_rows = (2 * n_om + 31) // 32 * 32  # GEMM rows computed (window rows, padded to 32)
+        flops = 3 * 2 * m_rows * 2 * L * n_seg * P * spec.n_k  # executed, 3 products
+        tf = flops / (k_ms * 1e-3) / 1e12
+        out["dtype"] = "f16x3" if args.form == "gemm_f16x3" else "bf16x3"
+        out["roofline"] = {
+            "bound": "mfma", "kernel": "seg_gemm_kernel (tiled ring)", "achieved": round(tf, 2),
+            "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4),
+            "kernel_ms": round(k_ms, 2), "traffic": None,
+            "note": "executed MFMA flops (3 split products of the real GEMM with "
+                    f"{m_rows} rows x {2 * L} per chunk) / the summed chunk-kernel time of "
+                    "all launches of the step; useful flops are one third",
+        }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(spec, L, H, args.cpu_pixels or 16,
