@@ -57,8 +57,9 @@ extern "C" {
 #define TACAW_MEAN_GLOBAL 0      /* mean over the frames that enter a chunk (default) */
 #define TACAW_MEAN_PER_SEGMENT 1 /* unweighted mean of each chunk's own L frames       */
                                  /* (scipy's detrend='constant'), removed exactly in   */
-                                 /* FP64; needs the FFT transform, a window whose DFT  */
-                                 /* lives on bins 0 and +-1, hop >= L/4 and n_frames   */
+                                 /* FP64; needs the FFT or bf16 GEMM transform, a      */
+                                 /* window whose DFT lives on bins 0 and +-1,          */
+                                 /* hop >= L/4 and n_frames                            */
                                  /* < 2^31, else UNSUPPORTED                           */
 #define TACAW_MEAN_NONE 2        /* keep the zero-loss peak (the paper's behaviour)   */
 

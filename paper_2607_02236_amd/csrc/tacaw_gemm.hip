@@ -439,7 +439,8 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
               }
             }
             if (corr) {
-              acc64[nb][q] += (double)xr * (double)xr + (double)xi * (double)xi;
+              // the per-chunk mean kernel supplies these rows' whole FP64 value
+              if (!a.corr_skip) acc64[nb][q] += (double)xr * (double)xr + (double)xi * (double)xi;
             } else {
               const float pw = xr * xr + xi * xi;
               acc64[nb][q] += (double)(pw * inv2[nb]);

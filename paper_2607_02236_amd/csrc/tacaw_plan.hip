@@ -483,8 +483,10 @@ int tacaw_plan_check(const tacaw_plan_desc* d) {
   if (transform_is_gemm(d->transform) && !seg_gemm_supported(d->seg_len))
     return fail(TACAW_ERR_UNSUPPORTED, "GEMM transform does not support this seg_len");
   if (d->mean_mode == TACAW_MEAN_PER_SEGMENT) {
-    if (d->transform != TACAW_FFT_F32)
-      return fail(TACAW_ERR_UNSUPPORTED, "per-segment mean needs the FFT transform");
+    if (d->transform == TACAW_GEMM_F16X3)
+      return fail(TACAW_ERR_UNSUPPORTED,
+                  "per-segment mean needs the FFT or bf16 GEMM transform (fp16 scales its "
+                  "operands from the whole series)");
     if ((d->seg_len + d->hop - 1) / d->hop > kMaxPsegOpen)
       return fail(TACAW_ERR_UNSUPPORTED, "per-segment mean needs hop >= seg_len / 4");
     if (d->n_frames >= ((int64_t)1 << 31))

@@ -50,7 +50,7 @@ def _ok(**over):
     (dict(ny=0), "INVALID_ARG"),
     (dict(window="hann_width", window_param=0.0), "INVALID_ARG"),
     (dict(window="tukey", window_param=1.5), "INVALID_ARG"),
-    (dict(mean_mode="per_segment", transform="gemm_bf16x3"), "UNSUPPORTED"),
+    (dict(mean_mode="per_segment", transform="gemm_f16x3"), "UNSUPPORTED"),
     (dict(mean_mode="per_segment", hop=31), "UNSUPPORTED"),  # more than 4 chunks per frame
     (dict(dt_fs=0.0), "INVALID_ARG"),
     (dict(n_det=2), "INVALID_ARG"),

@@ -142,6 +142,40 @@ def test_gemm_bf16_streamed_pushes(tacaw, ring, tiled):
     plan.close()
 
 
+@pytest.mark.parametrize("roi", [0, 60])
+def test_gemm_bf16_per_chunk_mean(tacaw, roi):
+    # per-chunk mean with the bf16 GEMM form: the FP64 per-chunk kernel supplies the
+    # correction rows, the GEMM kernel every other row; streamed pushes
+    L, H, NT, ny, nx, P, piece = 512, 256, 1536, 6, 7, 2, 192
+    spec = T.SeriesSpec(P, NT, ny, nx, dtype="c64", seed=77, model="lines", n_terms=8)
+    psi = T.generate(spec)
+    masks = T.standard_masks(ny, nx, scale=min(ny, nx) / 128)
+    from paper_2607_02236_amd import axes
+
+    M = axes.omega_half_for(L, 5.0, e_max_mev=roi) if roi else 0
+    plan = tacaw.Plan(P, ny, nx, NT, L, H, transform="gemm_bf16x3", mean_mode="per_segment",
+                      masks=torch.from_numpy(masks).cuda(), dt_fs=5.0, omega_half=M)
+    x = psi.cuda()
+    for f0 in range(0, NT, piece):
+        plan.push(x[:, f0:f0 + piece])
+    S = plan.finalize().cpu().numpy().reshape(plan.n_omega, -1)
+    D, Dp = plan.detector_spectra(per_probe=True)
+    torch.cuda.synchronize()
+    So, Spo = O.tacaw_spectra(psi.numpy(), L, H, O.window("hann", L), "per_segment")
+    rows = axes.window_rows(L, M)
+    So, Spo = So[rows], Spo[:, rows]
+    Do = O.detector_spectra(So, masks)
+    Dpo = np.transpose(O.detector_spectra(Spo, masks), (1, 0, 2))
+    e = max([rel(S, So)] + [rel(D.cpu().numpy()[j], Do[j]) for j in range(4)]
+            + [rel(Dp.cpu().numpy()[j], Dpo[j]) for j in range(4)])
+    corr = [int(np.flatnonzero(rows == b)[0]) for b in (0, 1, L - 1)]
+    eR = rel(S[corr], So[corr])
+    print(f"bf16x3 per-chunk mean (window {roi} meV, {plan.n_omega} bins): max rel err {e:.2e}, "
+          f"rows 0, +-1 {eR:.2e}")
+    assert e <= BARS["gemm_bf16x3"] and eR <= 1e-6
+    plan.close()
+
+
 def test_gemm_rejects_streaming_fp16_and_unsupported_lengths(tacaw):
     with pytest.raises(tacaw.TacawError) as e:
         tacaw.Plan(1, 4, 4, 400, 200, 100, transform="gemm_bf16x3")

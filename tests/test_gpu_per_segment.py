@@ -183,7 +183,7 @@ def test_per_segment_refusals(tacaw):
         tacaw.Plan(1, 4, 4, 256, 128, 64, window="tukey", window_param=0.3,
                    mean_mode="per_segment")
     assert e.value.kind == "UNSUPPORTED"
-    with pytest.raises(tacaw.TacawError) as e:  # the GEMM form subtracts one exact mean
+    with pytest.raises(tacaw.TacawError) as e:  # fp16 GEMM scales from the whole series
         tacaw.Plan(1, 4, 4, 256, 128, 64, transform="gemm_f16x3", mean_mode="per_segment")
     assert e.value.kind == "UNSUPPORTED"
 
