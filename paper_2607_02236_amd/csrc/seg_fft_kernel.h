@@ -277,9 +277,10 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
       };
       // The probe's first chunk fixes c: the window-weighted mean of the N1 frames
       // t = N2 n1 + N2 / 2, spread evenly over the chunk, which thread n2 = N2 / 2
-      // holds (FP64 sum, rounded to FP32 for complex64 input so that the FP32
-      // subtraction below is exact). Every value of c keeps the mean correction
-      // exact; one near the chunks' own mean keeps |X'| small at bins 0 and +-1,
+      // holds (FP64 sum, rounded to FP32 for complex64 input, so that the c
+      // subtracted in FP32 below is the c the correction uses). Every value of c
+      // keeps the mean correction exact; one near the chunks' own mean keeps |X'|
+      // small at bins 0 and +-1,
       // where the correction cancels. It depends only on the series, not on how
       // it was pushed.
       // raw(n1): the thread's raw sample n1 of the chunk, from a register array
