@@ -112,16 +112,17 @@ def test_gemm_chunk_length_1024(tacaw, form, roi):
     plan.close()
 
 
-@pytest.mark.parametrize("ring,tiled", [(0, False), (2048, False), (2048, True)])
-def test_gemm_bf16_streamed_pushes(tacaw, ring, tiled):
+@pytest.mark.parametrize("ring,tiled,dtype", [(0, False, "c64"), (2048, False, "c64"),
+                                              (2048, True, "c64"), (0, False, "c128")])
+def test_gemm_bf16_streamed_pushes(tacaw, ring, tiled, dtype):
     # the streaming form: a reference fixed by the first chunk and the exact FP64
     # mean correction, frames before a push from the ring (immediate, deferred, tiled)
     L, H, NT, ny, nx, P, piece = 1024, 512, 3072, 5, 13, 2, 256
-    spec = T.SeriesSpec(P, NT, ny, nx, dtype="c64", seed=98, model="lines", n_terms=8)
+    spec = T.SeriesSpec(P, NT, ny, nx, dtype=dtype, seed=98, model="lines", n_terms=8)
     psi = T.generate(spec)
     masks = T.standard_masks(ny, nx, scale=min(ny, nx) / 128)
     masks[3] = np.random.default_rng(5).random((ny, nx))
-    plan = tacaw.Plan(P, ny, nx, NT, L, H, transform="gemm_bf16x3",
+    plan = tacaw.Plan(P, ny, nx, NT, L, H, transform="gemm_bf16x3", in_dtype=dtype,
                       masks=torch.from_numpy(masks).cuda(), ring_frames=ring, tiled_ring=tiled)
     x = psi.cuda()
     for f0 in range(0, NT, piece):
@@ -136,7 +137,7 @@ def test_gemm_bf16_streamed_pushes(tacaw, ring, tiled):
             + [rel(Dp.cpu().numpy()[j], Dpo[j]) for j in range(4)])
     rows = [0, 1, L - 1]
     eR = rel(S[rows], So[rows])
-    print(f"bf16x3 streamed (ring {ring}{' tiled' if tiled else ''}): max rel err {e:.2e}, "
+    print(f"bf16x3 streamed {dtype} (ring {ring}{' tiled' if tiled else ''}): max rel err {e:.2e}, "
           f"rows 0, +-1 {eR:.2e}")
     assert e <= BARS["gemm_bf16x3"] and eR <= BARS["gemm_bf16x3"]
     plan.close()
