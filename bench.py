@@ -312,7 +312,8 @@ def main():
     # the same bytes in the chunk transform's pattern: tile-wide columns across frames
     seg = plan.info()["tile_pixels"] * psi.element_size()
     col_ms = []
-    if seg in (64, 128, 256, 512) and (spec.n_k * psi.element_size()) % seg == 0:
+    row_bytes = spec.n_k * psi.element_size()
+    if seg in (64, 128, 256, 512) and row_bytes % seg == 0 and row_bytes // seg <= 65535:
         for _ in range(3):
             c0 = torch.cuda.Event(enable_timing=True)
             c1 = torch.cuda.Event(enable_timing=True)
