@@ -42,6 +42,8 @@ extern "C" {
 #define TACAW_ERR_OOM (-4)         /* device allocation failed or size too large   */
 #define TACAW_ERR_HIP (-5)         /* a HIP runtime call failed                    */
 #define TACAW_ERR_UNSUPPORTED (-6) /* valid but not implemented combination        */
+#define TACAW_ERR_NONFINITE (-7)   /* finalize with TACAW_FLAG_CHECK_FINITE found NaN  */
+                                   /* or Inf in S or D_p (the plan is finalized)     */
 
 /* ---- window w(t), t = 0..L-1 (Sec. II.B.2; Sec. III.A) ------------------ */
 #define TACAW_WIN_HANN 0       /* periodic Hann 1/2 - 1/2 cos(2 pi t / L) (default)   */
@@ -149,6 +151,12 @@ typedef struct {
  * tacaw_ingest_frames_tiled (tacaw_ingest_frames fails with STATE on such a
  * plan). */
 #define TACAW_FLAG_TILED_RING 2
+/* flags: finalize counts the non-finite values of S and of the per-probe detector
+ * spectra after normalisation (NaN or Inf exit waves propagate into them; without
+ * the flag nothing checks). If any is found, finalize still completes (S written,
+ * the plan finalized) but returns TACAW_ERR_NONFINITE; tacaw_plan_info.nonfinite
+ * holds the count. The check synchronizes with the plan's stream. */
+#define TACAW_FLAG_CHECK_FINITE 4
 
 typedef struct {
   int32_t n_segments;     /* N_s                                                     */
@@ -160,7 +168,8 @@ typedef struct {
   int32_t probes_complete;/* probes whose whole series has been pushed               */
   double window_sum_sq;   /* sum_t w(t)^2                                            */
   int32_t tile_pixels;    /* pixels per workgroup tile of the push kernel            */
-  int32_t reserved;
+  int32_t nonfinite;      /* non-finite values in S and D_p at finalize (flag        */
+                          /* TACAW_FLAG_CHECK_FINITE; clipped to 2^31 - 1), else 0    */
   double last_chunk_kernel_ms; /* last push's chunk kernel in ms (flag set), or -1   */
 } tacaw_plan_info;
 

@@ -745,4 +745,22 @@ hipError_t launch_sum(const double* p, int64_t n, double* out, hipStream_t st) {
   return launch_dot_gS(p, nullptr, n, out, st);
 }
 
+// *cnt += number of non-finite values (NaN or +-Inf) in x[0..n)
+__global__ void count_nonfinite_kernel(const double* __restrict__ x, int64_t n,
+                                       unsigned long long* cnt) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    c += isfinite(x[i]) ? 0ull : 1ull;
+  if (c) atomicAdd(cnt, c);
+}
+
+hipError_t launch_count_nonfinite(const double* x, int64_t n, unsigned long long* cnt,
+                                  hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(count_nonfinite_kernel, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, st, x,
+                     n, cnt);
+  return hipGetLastError();
+}
+
 }  // namespace tacaw

@@ -213,5 +213,8 @@ hipError_t launch_mean_exact(const void* in, int in_dtype, int64_t pstride, int6
 hipError_t launch_dot_gS(const double* S, const double* gS, int64_t n, double* out,
                          hipStream_t st);
 hipError_t launch_sum(const double* p, int64_t n, double* out, hipStream_t st);
+// *cnt += the count of NaN and Inf values in x[0..n) (the caller zeroes *cnt)
+hipError_t launch_count_nonfinite(const double* x, int64_t n, unsigned long long* cnt,
+                                  hipStream_t st);
 
 }  // namespace tacaw

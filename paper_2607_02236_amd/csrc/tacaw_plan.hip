@@ -206,6 +206,8 @@ struct tacaw_plan_s {
   int64_t scratch_bytes = 0;
   float* gscale = nullptr;  // GEMM form: [P][n_k]
   double* qfac = nullptr;   // [n_om] quantum-statistics factor per row (temperature > 0)
+  unsigned long long* nf = nullptr;  // non-finite count at finalize (TACAW_FLAG_CHECK_FINITE)
+  int64_t nonfinite = 0;
   hipEvent_t ev[kMaxTimed][2] = {};  // chunk-kernel timing, up to kMaxTimed launches per push
   int n_timed = 0;                    // launches timed in the last push
   int64_t D = 0;                      // ring depth (frames per slot)
@@ -652,6 +654,7 @@ int tacaw_plan(const tacaw_plan_desc* d, void* hip_stream, tacaw_plan_t* out) {
   A((void**)&P->msum, np * nk * 16, "mean sums");
   A((void**)&P->xs, np * kMaxCorr * nk * 16, "correction sums");
   A((void**)&P->S, (int64_t)P->n_om * nk * 8, "spectrum accumulator");
+  if (d->flags & TACAW_FLAG_CHECK_FINITE) A((void**)&P->nf, 8, "non-finite count");
   if (d->mean_mode == TACAW_MEAN_PER_SEGMENT) {
     P->pseg_V = (P->L + P->H - 1) / P->H;
     A((void**)&P->pseg_tw, (int64_t)kMaxCorr * P->L * 16, "per-chunk mean twiddles");
@@ -797,6 +800,7 @@ int tacaw_plan_get_info(tacaw_plan_t P, tacaw_plan_info* info) {
   info->probes_complete = c;
   info->window_sum_sq = P->sumw2;
   info->tile_pixels = P->W;
+  info->nonfinite = (int32_t)std::min<int64_t>(P->nonfinite, 0x7FFFFFFF);
   info->last_chunk_kernel_ms = -1.0;
   if (P->n_timed > 0) {
     double tot = 0.0;
@@ -1084,6 +1088,25 @@ int tacaw_finalize(tacaw_plan_t P, double* d_S) {
                                     kappa_probe(P), P->qfac, 1, P->n_om, P->st),
                   "normalisation"));
   P->state = 1;
+  P->nonfinite = 0;
+  if (P->nf) {
+    // NaN or Inf in the exit waves propagate into S and D_p: count them
+    unsigned long long h = 0;
+    TRY(hip_check(launch_fill_zero(P->nf, 8, P->st), "non-finite check"));
+    TRY(hip_check(launch_count_nonfinite(P->S, (int64_t)P->n_om * P->n_k, P->nf, P->st),
+                  "non-finite check"));
+    if (P->d.n_det > 0)
+      TRY(hip_check(launch_count_nonfinite(P->Dp, (int64_t)P->d.n_det * P->d.n_probe * P->n_om,
+                                           P->nf, P->st),
+                    "non-finite check"));
+    TRY(hip_check(hipMemcpyAsync(&h, P->nf, 8, hipMemcpyDeviceToHost, P->st), "non-finite check"));
+    TRY(hip_check(hipStreamSynchronize(P->st), "non-finite check"));
+    P->nonfinite = (int64_t)h;
+    if (h > 0)
+      return fail(TACAW_ERR_NONFINITE, std::to_string(h) +
+                                           " non-finite values in S and D_p (NaN or Inf in the "
+                                           "exit waves)");
+  }
   return TACAW_OK;
 }
 

@@ -15,10 +15,12 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 FLAG_TIME_KERNELS = 1  # TACAW_FLAG_TIME_KERNELS
 FLAG_TILED_RING = 2  # TACAW_FLAG_TILED_RING
+FLAG_CHECK_FINITE = 4  # TACAW_FLAG_CHECK_FINITE
 LIB_PATH = os.environ.get("TACAW_LIB") or os.path.join(_HERE, "libtacaw.so")
 
 OK = 0
-ERR = {-1: "INVALID_ARG", -2: "SHAPE", -3: "STATE", -4: "OOM", -5: "HIP", -6: "UNSUPPORTED"}
+ERR = {-1: "INVALID_ARG", -2: "SHAPE", -3: "STATE", -4: "OOM", -5: "HIP", -6: "UNSUPPORTED",
+       -7: "NONFINITE"}
 WINDOWS = {"hann": 0, "rect": 1, "hann_width": 2, "tukey": 3, "custom": 4}
 MEANS = {"global": 0, "per_segment": 1, "none": 2}
 TRANSFORMS = {"fft": 0, "gemm_bf16x3": 1, "gemm_f16x3": 2}
@@ -53,7 +55,7 @@ class PlanInfo(C.Structure):
         ("n_segments", C.c_int32), ("n_omega", C.c_int32),
         ("frames_used", C.c_int64), ("frames_dropped", C.c_int64), ("device_bytes", C.c_int64),
         ("state", C.c_int32), ("probes_complete", C.c_int32),
-        ("window_sum_sq", C.c_double), ("tile_pixels", C.c_int32), ("reserved", C.c_int32),
+        ("window_sum_sq", C.c_double), ("tile_pixels", C.c_int32), ("nonfinite", C.c_int32),
         ("last_chunk_kernel_ms", C.c_double),
     ]
 
@@ -177,14 +179,16 @@ class Plan:
     masks: optional torch float64 CUDA tensor [n_det, ny, nx] (enables the fused
     per-probe detector spectra). ring_frames > seg_len: deferred streaming ring;
     tiled_ring: store that ring per pixel tile (hop = seg_len / 2; pushes, or a
-    producer through ingest_tiled).
+    producer through ingest_tiled). check_finite: finalize counts NaN and Inf in S
+    and D_p and raises TacawError (kind NONFINITE) if there are any; the plan is
+    finalized all the same.
     """
 
     def __init__(self, n_probe, ny, nx, n_frames, seg_len, hop=None, window="hann",
                  window_param=1.0, mean_mode="global", transform="fft", in_dtype="c64",
                  probe_reduce="mean", dt_fs=5.0, masks=None, max_probes_in_flight=0,
                  stream=None, time_kernels=False, temperature_K=0.0, omega_half=0,
-                 ring_frames=0, k_row_stride=0, tiled_ring=False):
+                 ring_frames=0, k_row_stride=0, tiled_ring=False, check_finite=False):
         self.handle = None
         hop = seg_len // 2 if hop is None else hop
         self.n_probe, self.ny, self.nx = int(n_probe), int(ny), int(nx)
@@ -208,7 +212,8 @@ class Plan:
                               mean_mode, transform, in_dtype, probe_reduce, dt_fs, n_det, mptr,
                               max_probes_in_flight,
                               (FLAG_TIME_KERNELS if time_kernels else 0)
-                              | (FLAG_TILED_RING if tiled_ring else 0), temperature_K,
+                              | (FLAG_TILED_RING if tiled_ring else 0)
+                              | (FLAG_CHECK_FINITE if check_finite else 0), temperature_K,
                               omega_half=omega_half, ring_frames=ring_frames,
                               k_row_stride=k_row_stride)
         self.row_stride = int(k_row_stride) or self.nx
@@ -222,7 +227,7 @@ class Plan:
     def info(self) -> dict:
         inf = PlanInfo()
         _check(lib.tacaw_plan_get_info(self.handle, C.byref(inf)))
-        return {f: getattr(inf, f) for f, _ in PlanInfo._fields_ if f != "reserved"}
+        return {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
 
     @property
     def n_omega(self):
@@ -287,7 +292,12 @@ class Plan:
             out = torch.empty((self.n_omega, self.ny, self.nx), dtype=torch.float64, device="cuda")
         if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != self.n_omega * self.ny * self.nx:
             raise ValueError("out must be a contiguous float64 [n_omega, ny, nx] tensor")
-        _check(lib.tacaw_finalize(self.handle, C.c_void_p(out.data_ptr())))
+        rc = lib.tacaw_finalize(self.handle, C.c_void_p(out.data_ptr()))
+        if rc == -7:  # NONFINITE: finalized all the same; the spectrum rides on the error
+            err = TacawError(rc, lib.tacaw_last_error().decode())
+            err.result = out
+            raise err
+        _check(rc)
         return out
 
     def detector_spectra(self, masks=None, per_probe=False, out=None, out_p=None):

@@ -257,7 +257,8 @@ int main() {
     d.n_frames = 2 * L;
     d.k_row_stride = 11;
     d.probe_reduce = TACAW_PROBE_SUM;
-    std::snprintf(what, sizeof what, "L %d k window, sum", L);
+    d.flags = TACAW_FLAG_CHECK_FINITE | TACAW_FLAG_TIME_KERNELS;
+    std::snprintf(what, sizeof what, "L %d k window, sum, finite check", L);
     accepted(d, what);
   }
 

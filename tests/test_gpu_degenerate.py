@@ -1,6 +1,7 @@
 """Degenerate shapes against the FP64 oracle: a single pixel (one valid lane in a
 tile), a series exactly one chunk long, a hop of one frame (every frame starts a
-chunk), and a push of zero frames through the C ABI (a no-op)."""
+chunk), and a push of zero frames through the C ABI (a no-op); and non-finite
+exit waves, which the optional finite check reports at finalize."""
 
 import ctypes
 
@@ -68,3 +69,46 @@ def test_zero_frame_push_is_a_no_op():
     S = plan.finalize().cpu()
     plan.close()
     assert torch.equal(S, S_ref)
+
+
+def test_nonfinite_input_is_reported_with_the_check_flag():
+    # a NaN and an Inf exit wave propagate into their pixels' spectra; with
+    # check_finite the finalize reports them (NONFINITE, plan finalized, count in
+    # info); without it nothing checks; clean input passes the check
+    from paper_2607_02236_amd import tacaw
+
+    L, H, NT, ny, nx, P = 128, 64, 320, 3, 4, 2
+    spec = T.SeriesSpec(P, NT, ny, nx, dtype="c64", seed=17, model="lines", n_terms=4)
+    clean = T.generate(spec).cuda()
+    bad = clean.clone()
+    bad[0, 100, 1, 2] = complex(float("nan"), 0.0)
+    bad[1, 7, 2, 0] = complex(float("inf"), 1.0)
+    masks = torch.from_numpy(T.standard_masks(ny, nx, scale=0.1)).cuda()
+
+    plan = tacaw.Plan(P, ny, nx, NT, L, H, masks=masks, check_finite=True)
+    plan.push(clean)
+    S = plan.finalize()
+    assert plan.info()["nonfinite"] == 0 and torch.isfinite(S).all()
+    plan.close()
+
+    plan = tacaw.Plan(P, ny, nx, NT, L, H, masks=masks, check_finite=True)
+    plan.push(bad)
+    with pytest.raises(tacaw.TacawError) as e:
+        plan.finalize()
+    assert e.value.kind == "NONFINITE"
+    S = e.value.result
+    n = plan.info()["nonfinite"]
+    bad_S = int((~torch.isfinite(S)).sum())
+    print(f"non-finite values reported {n}, in S {bad_S}", flush=True)
+    assert plan.info()["state"] == 1 and n >= bad_S > 0
+    # only the two poisoned pixels' columns of S are affected
+    cols = (~torch.isfinite(S)).reshape(L, -1).any(dim=0).nonzero().flatten().tolist()
+    assert cols == sorted([1 * nx + 2, 2 * nx + 0])
+    D, Dp = plan.detector_spectra(per_probe=True)  # the plan is usable after the report
+    plan.close()
+
+    plan = tacaw.Plan(P, ny, nx, NT, L, H, masks=masks)
+    plan.push(bad)
+    S = plan.finalize()  # no check: the NaN propagates silently
+    assert not torch.isfinite(S).all() and plan.info()["nonfinite"] == 0
+    plan.close()
