@@ -299,6 +299,38 @@ int tacaw_backward_static(tacaw_plan_t plan, const void* d_frames, int32_t probe
  * the same shape (buffers are kept). */
 int tacaw_reset(tacaw_plan_t plan);
 
+/* Checkpoint and resume of a long run. The result is a sum over chunks and
+ * probe batches, each batch adding its share to a stored array (Sec. II.B's
+ * Calculator paragraph, Eq. 2), so the accumulators after some probes are the
+ * complete state of the run: a job that stops there can carry on in a new
+ * process from a copy of them.
+ *
+ * tacaw_plan_export writes that state to the host buffer h_buf (caller-owned,
+ * buf_bytes long): a header (format tag, a fingerprint of the descriptor fields,
+ * window and detector masks the state depends on, the sizes, frames dropped),
+ * the frame cursor of every probe, then S, the per-probe mean references, mean
+ * and correction sums, the per-probe detector spectra and, with the per-chunk
+ * mean, its correction sums, references and chunk means, as stored on the
+ * device (FP64). The format is for the same library build and byte order.
+ * It synchronises the plan's stream. *bytes_needed (if not NULL) receives the
+ * size; with h_buf NULL only the size is returned (any state). Allowed only on
+ * an open plan at a probe boundary: every probe untouched or complete (cursor 0
+ * or >= frames_used), no ingest open. Errors: INVALID_ARG (NULL plan), SHAPE
+ * (buffer too small), STATE (finalized, or a probe partially pushed), HIP.
+ *
+ * tacaw_plan_import loads such a state into a plan built from the same
+ * descriptor and mask values (the pointers and stream may differ) that has had
+ * no frames pushed since its creation or last reset; the plan then continues
+ * as the exporting one would: pushing the remaining probes as an uninterrupted
+ * run does gives bitwise its S, and its detector spectra up to the order of
+ * their FP64 atomic sums (which varies between any two runs). Errors:
+ * INVALID_ARG (NULL, not a
+ * state, or a cursor off a probe boundary), SHAPE (another descriptor, or bytes
+ * shorter than the state), STATE (finalized, frames pushed, ingest open), HIP;
+ * on an error the plan is unchanged, except after HIP (reset it). */
+int tacaw_plan_export(tacaw_plan_t plan, void* h_buf, int64_t buf_bytes, int64_t* bytes_needed);
+int tacaw_plan_import(tacaw_plan_t plan, const void* h_buf, int64_t bytes);
+
 /* Replace the stream used for subsequent calls. */
 int tacaw_set_stream(tacaw_plan_t plan, void* hip_stream);
 

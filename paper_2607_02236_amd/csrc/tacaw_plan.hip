@@ -821,6 +821,159 @@ int tacaw_plan_get_info(tacaw_plan_t P, tacaw_plan_info* info) {
 
 void tacaw_destroy(tacaw_plan_t P) { delete P; }
 
+// ---- checkpoint: the accumulator state at a probe boundary ----
+namespace {
+constexpr uint64_t kStateMagic = 0x31305354574154ull;  // "TAWTS01"
+struct StateHeader {
+  uint64_t magic;
+  uint64_t fingerprint;  // of the descriptor fields the state depends on
+  int64_t total_bytes;
+  int32_t n_probe, n_k, n_om, n_det;
+  int32_t per_chunk, s_defined;
+  int64_t dropped;
+};
+
+// FNV-1a over the descriptor fields (no pointers or stream), the window values and
+// the detector masks (copied back from the plan; synchronises its stream)
+int state_fingerprint(tacaw_plan_s* P, uint64_t* out) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  };
+  const tacaw_plan_desc& d = P->d;
+  const int32_t tiled = (d.flags & TACAW_FLAG_TILED_RING) ? 1 : 0;
+  mix(&d.n_probe, 4); mix(&d.ny, 4); mix(&d.nx, 4); mix(&d.n_frames, 8); mix(&d.seg_len, 4);
+  mix(&d.hop, 4); mix(&d.window, 4); mix(&d.window_param, 8); mix(&d.mean_mode, 4);
+  mix(&d.transform, 4); mix(&d.in_dtype, 4); mix(&d.probe_reduce, 4); mix(&d.n_det, 4);
+  mix(&d.temperature_K, 8); mix(&d.ring_frames, 8); mix(&d.omega_half, 4); mix(&tiled, 4);
+  mix(P->win.data(), P->win.size() * sizeof(double));
+  if (P->d.n_det > 0) {
+    std::vector<double> m((size_t)P->d.n_det * P->n_k);
+    if (hipMemcpyAsync(m.data(), P->masks, m.size() * 8, hipMemcpyDeviceToHost, P->st) != hipSuccess ||
+        hipStreamSynchronize(P->st) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(TACAW_ERR_HIP, "state fingerprint: mask copy failed");
+    }
+    mix(m.data(), m.size() * 8);
+  }
+  *out = h;
+  return TACAW_OK;
+}
+
+// the device arrays of the state, in order: S, references, mean sums, correction
+// sums, per-probe detector spectra, and the per-chunk mean's corrections,
+// references and chunk means
+std::vector<std::pair<void*, int64_t>> state_arrays(tacaw_plan_s* P) {
+  const int64_t nk = P->n_k, np = P->d.n_probe;
+  std::vector<std::pair<void*, int64_t>> a = {
+      {P->S, (int64_t)P->n_om * nk * 8},
+      {P->cref, np * nk * 16},
+      {P->msum, np * nk * 16},
+      {P->xs, np * kMaxCorr * nk * 16}};
+  if (P->Dp) a.push_back({P->Dp, (int64_t)P->d.n_det * np * P->n_om * 8});
+  if (P->pcorr) {
+    a.push_back({P->pcorr, np * kMaxCorr * nk * 8});
+    a.push_back({P->pref, np * nk * 16});
+    if (P->cmean) a.push_back({P->cmean, np * (int64_t)P->Ns * nk * 16});
+  }
+  return a;
+}
+
+int64_t state_bytes(tacaw_plan_s* P) {
+  int64_t b = (int64_t)sizeof(StateHeader) + (int64_t)P->d.n_probe * 8;
+  for (auto& x : state_arrays(P)) b += x.second;
+  return b;
+}
+
+// every probe is untouched or complete, nothing in flight
+bool at_probe_boundary(const tacaw_plan_s* P) {
+  if (P->ingest_open) return false;
+  for (int64_t c : P->cursor)
+    if (c != 0 && c < P->n_used) return false;
+  return true;
+}
+}  // namespace
+
+int tacaw_plan_export(tacaw_plan_t P, void* h_buf, int64_t buf_bytes, int64_t* bytes_needed) {
+  g_err.clear();
+  if (!P) return fail(TACAW_ERR_INVALID_ARG, "plan is NULL");
+  const int64_t need = state_bytes(P);
+  if (bytes_needed) *bytes_needed = need;
+  if (!h_buf) return TACAW_OK;
+  if (buf_bytes < need) return fail(TACAW_ERR_SHAPE, "buffer smaller than the state");
+  if (P->state != 0) return fail(TACAW_ERR_STATE, "plan is finalized");
+  if (!at_probe_boundary(P))
+    return fail(TACAW_ERR_STATE, "a probe is partially pushed: export at a probe boundary");
+  StateHeader h{};
+  h.magic = kStateMagic;
+  TRY(state_fingerprint(P, &h.fingerprint));
+  h.total_bytes = need;
+  h.n_probe = P->d.n_probe;
+  h.n_k = P->n_k;
+  h.n_om = P->n_om;
+  h.n_det = P->d.n_det;
+  h.per_chunk = P->pcorr ? 1 : 0;
+  h.s_defined = P->s_fresh ? 0 : 1;
+  h.dropped = P->dropped;
+  char* out = (char*)h_buf;
+  std::memcpy(out, &h, sizeof h);
+  out += sizeof h;
+  std::memcpy(out, P->cursor.data(), (size_t)P->d.n_probe * 8);
+  out += (int64_t)P->d.n_probe * 8;
+  for (auto& x : state_arrays(P)) {
+    if (x.first == P->S && P->s_fresh) {
+      std::memset(out, 0, (size_t)x.second);  // no chunk launched since the reset
+    } else {
+      TRY(hip_check(hipMemcpyAsync(out, x.first, (size_t)x.second, hipMemcpyDeviceToHost, P->st),
+                    "state export"));
+    }
+    out += x.second;
+  }
+  TRY(hip_check(hipStreamSynchronize(P->st), "state export"));
+  return TACAW_OK;
+}
+
+int tacaw_plan_import(tacaw_plan_t P, const void* h_buf, int64_t bytes) {
+  g_err.clear();
+  if (!P || !h_buf) return fail(TACAW_ERR_INVALID_ARG, "plan and buffer must not be NULL");
+  if (P->state != 0 || P->ingest_open)
+    return fail(TACAW_ERR_STATE, "import into an open plan with nothing in flight");
+  for (int64_t c : P->cursor)
+    if (c != 0) return fail(TACAW_ERR_STATE, "import into a plan with no frames pushed");
+  if (bytes < (int64_t)sizeof(StateHeader)) return fail(TACAW_ERR_SHAPE, "state buffer too small");
+  StateHeader h;
+  std::memcpy(&h, h_buf, sizeof h);
+  if (h.magic != kStateMagic) return fail(TACAW_ERR_INVALID_ARG, "not a plan state");
+  uint64_t fp = 0;
+  TRY(state_fingerprint(P, &fp));
+  if (h.fingerprint != fp || h.n_probe != P->d.n_probe || h.n_k != P->n_k ||
+      h.n_om != P->n_om || h.n_det != P->d.n_det || h.per_chunk != (P->pcorr ? 1 : 0))
+    return fail(TACAW_ERR_SHAPE, "the state belongs to a plan with another descriptor");
+  const int64_t need = state_bytes(P);
+  if (h.total_bytes != need || bytes < need) return fail(TACAW_ERR_SHAPE, "state buffer truncated");
+  const char* in = (const char*)h_buf + sizeof h;
+  std::vector<int64_t> cur((size_t)P->d.n_probe);
+  std::memcpy(cur.data(), in, (size_t)P->d.n_probe * 8);
+  in += (int64_t)P->d.n_probe * 8;
+  for (int64_t c : cur)
+    if (c < 0 || (c != 0 && c < P->n_used) || c > P->d.n_frames)
+      return fail(TACAW_ERR_INVALID_ARG, "state holds a probe cursor off a probe boundary");
+  for (auto& x : state_arrays(P)) {
+    TRY(hip_check(hipMemcpyAsync(x.first, in, (size_t)x.second, hipMemcpyHostToDevice, P->st),
+                  "state import"));
+    in += x.second;
+  }
+  TRY(hip_check(hipStreamSynchronize(P->st), "state import"));
+  for (int p = 0; p < P->d.n_probe; ++p) {
+    P->cursor[p] = cur[p];
+    P->s_done[p] = cur[p] >= P->n_used ? P->Ns : 0;
+  }
+  P->s_fresh = h.s_defined == 0;
+  P->dropped = h.dropped;
+  return TACAW_OK;
+}
+
 // Per-chunk mean: stream frames [a, min(b, n_used)) of a push through the FP64
 // chunk sums (after the references exist).
 static int run_pseg(tacaw_plan_t P, const void* frames, int64_t pstride, int64_t fstride,

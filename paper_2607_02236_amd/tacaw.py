@@ -96,6 +96,8 @@ def _load():
         "tacaw_synth_frames": (C.c_int, [C.POINTER(SynthDesc), P, C.c_int32, C.c_int32, C.c_int64,
                                          C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int32, P]),
         "tacaw_reset": (C.c_int, [P]),
+        "tacaw_plan_export": (C.c_int, [P, P, C.c_int64, C.POINTER(C.c_int64)]),
+        "tacaw_plan_import": (C.c_int, [P, P, C.c_int64]),
         "tacaw_set_stream": (C.c_int, [P, P]),
         "tacaw_plan_get_info": (C.c_int, [P, C.POINTER(PlanInfo)]),
         "tacaw_destroy": (None, [P]),
@@ -115,7 +117,7 @@ lib = _load()
 EXPORTED = ("tacaw_plan", "tacaw_plan_check", "tacaw_push_frames", "tacaw_ingest_frames",
             "tacaw_commit_frames", "tacaw_ingest_frames_tiled", "tacaw_finalize",
             "tacaw_detector_spectra", "tacaw_backward", "tacaw_backward_static", "tacaw_reset",
-            "tacaw_set_stream",
+            "tacaw_set_stream", "tacaw_plan_export", "tacaw_plan_import",
             "tacaw_plan_get_info", "tacaw_destroy", "tacaw_last_error", "tacaw_version",
             "tacaw_read_probe", "tacaw_read_probe_columns", "tacaw_synth_frames")
 
@@ -350,6 +352,21 @@ class Plan:
 
     def reset(self):
         _check(lib.tacaw_reset(self.handle))
+
+    def export_state(self) -> bytes:
+        """The accumulator state at a probe boundary (every probe untouched or
+        complete), as bytes that import_state of a plan with the same descriptor
+        and masks takes to continue the run."""
+        n = C.c_int64(0)
+        _check(lib.tacaw_plan_export(self.handle, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib.tacaw_plan_export(self.handle, buf, n.value, C.byref(n)))
+        return buf.raw
+
+    def import_state(self, state: bytes):
+        """Load a state from export_state into this plan (no frames pushed since
+        its creation or last reset)."""
+        _check(lib.tacaw_plan_import(self.handle, state, len(state)))
 
     def set_stream(self, stream):
         self.stream, sptr = _stream_ptr(stream)

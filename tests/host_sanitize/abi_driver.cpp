@@ -287,6 +287,11 @@ int main() {
   expect(tacaw_reset(nullptr) == TACAW_ERR_INVALID_ARG, "reset NULL", 0);
   expect(tacaw_set_stream(nullptr, nullptr) == TACAW_ERR_INVALID_ARG, "set_stream NULL", 0);
   expect(tacaw_plan_get_info(nullptr, &info) == TACAW_ERR_INVALID_ARG, "info NULL", 0);
+  unsigned char state[64] = {0};
+  expect(tacaw_plan_export(nullptr, state, sizeof state, &a) == TACAW_ERR_INVALID_ARG,
+         "export NULL", 0);
+  expect(tacaw_plan_import(nullptr, state, sizeof state) == TACAW_ERR_INVALID_ARG, "import NULL",
+         0);
   tacaw_destroy(nullptr);
 
   // ---- producer and read probes: argument checks ----

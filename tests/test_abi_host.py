@@ -109,6 +109,9 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.tacaw_finalize(None, None) == -1
     assert lib.tacaw_detector_spectra(None, None, 0, None, None) == -1
     assert lib.tacaw_reset(None) == -1
+    n = ctypes.c_int64(0)
+    assert lib.tacaw_plan_export(None, None, 0, ctypes.byref(n)) == -1
+    assert lib.tacaw_plan_import(None, b"\0" * 64, 64) == -1
     assert lib.tacaw_read_probe(None, 16, None, None) == -1
     lib.tacaw_destroy(None)
 
