@@ -407,13 +407,19 @@ __global__ void __launch_bounds__(64 * kGemmWaves)
           }
         }
       }
-      // one wave per SIMD issues in order: interleave the conversion (VALU) and
-      // the LDS reads with the MFMAs, so that they run while the matrix core works
+      // one wave per SIMD issues in order: interleave the conversion (VALU) with the
+      // MFMAs, so that it runs while the matrix core works, and issue the next
+      // k-step's B fragments (2 NB LDS reads) before this k-step's 3 NB MFMAs, which
+      // then hide their latency (each read placed just before its MFMA waited for it)
 #pragma unroll
-      for (int i = 0; i < 3 * NB * KSTEPS; ++i) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-        __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // VALU
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+      for (int kst = 0; kst < KSTEPS; ++kst) {
+        if (kst == 0) __builtin_amdgcn_sched_group_barrier(0x100, (KSTEPS > 1 ? 4 : 2) * NB, 0);
+        else if (kst + 1 < KSTEPS) __builtin_amdgcn_sched_group_barrier(0x100, 2 * NB, 0);
+#pragma unroll
+        for (int i = 0; i < 3 * NB; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+          __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // VALU
+        }
       }
       if (st % SPC == SPC - 1 && active) {
         // chunk complete: |X|^2 into the FP64 accumulators. Accumulator v of a lane
