@@ -116,6 +116,54 @@ def cpu_baseline(spec, L, H, n_pix, seed=0, gradient=False, mean_mode="global", 
                       f"{psi.shape[1]} frames of {n_pix} seeded pixels ({dt:.1f} s)"}
 
 
+def compare_forms(psi, spec, L, H, masks, stream, e_max_mev=100.0, steps=3):
+    """FFT vs DFT-GEMM on the same resident series at one energy window: each form's
+    chunk-kernel time (HIP events, mean of `steps` after one warm-up) and the GEMM
+    forms' executed MFMA rate, with the relative L2 difference of their S from the
+    FFT form's S (whose own error against the FP64 oracle the parity tests bound at
+    about 1e-7, so the difference is the GEMM form's error at that accuracy)."""
+    import numpy as np
+    import torch
+
+    from paper_2607_02236_amd import axes, tacaw
+
+    M = axes.omega_half_for(L, 5.0, e_max_mev=e_max_mev)
+    res, S_ref = {}, None
+    for form in ("fft", "gemm_bf16x3", "gemm_f16x3"):
+        plan = tacaw.Plan(spec.n_probe, spec.ny, spec.nx, spec.n_frames, L, H, masks=masks,
+                          transform=form, in_dtype=spec.dtype, time_kernels=True, stream=stream,
+                          dt_fs=5.0, omega_half=M)
+        S = torch.empty((plan.n_omega, spec.ny, spec.nx), dtype=torch.float64, device="cuda")
+        k_ms = []
+        for i in range(steps + 1):
+            plan.reset()
+            plan.push(psi)
+            plan.finalize(S)
+            if i:
+                k_ms.append(plan.info()["last_chunk_kernel_ms"])
+        torch.cuda.synchronize()
+        t = float(np.mean(k_ms))
+        r = {"kernel_ms": round(t, 4), "exit_wave_gbs": round(spec.nbytes / (t * 1e-3) / 1e9, 1)}
+        if form == "fft":
+            S_ref = S
+        else:
+            m_rows = (2 * plan.n_omega + 31) // 32 * 32
+            flops = 3 * 2 * m_rows * 2 * L * plan.info()["n_segments"] * spec.n_probe * spec.n_k
+            tf = flops / (t * 1e-3) / 1e12
+            r.update(mfma_tflops=round(tf, 1), mfma_frac=round(tf / 2500.0, 4),
+                     rel_diff_vs_fft=float(torch.linalg.vector_norm(S - S_ref)
+                                           / torch.linalg.vector_norm(S_ref)))
+            r["speed_vs_fft"] = round(res["fft"]["kernel_ms"] / t, 3)
+        res[form] = r
+        log(f"form comparison: {form} {t:.3f} ms")
+        plan.close()
+    res.update(energy_window_mev=e_max_mev, n_omega=2 * M + 1,
+               note="same resident series, energy window |E| <= 100 meV (the DFT-GEMM forms "
+                    "compute only its rows); chunk-kernel times by HIP events; MFMA flops are "
+                    "the executed 3 split products")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +208,8 @@ def main():
     ap.add_argument("--cpu-pixels", type=int, default=0,
                     help="pixels of the oracle's sample (default 4096; 16 with --producer)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-form-compare", action="store_true",
+                    help="skip the FFT vs DFT-GEMM comparison of the default workload")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -428,6 +478,10 @@ def main():
         # the chunk kernel's loads alone, in its own tile pattern: its HBM rate against that
         out["roofline"]["tile_pattern_read_ceiling_gbs"] = round(col_ceiling, 1)
         out["roofline"]["kernel_frac_of_tile_pattern_ceiling"] = round(achieved / col_ceiling, 4)
+    if (args.form == "fft" and not streaming and not gradient and args.mean_mode == "global"
+            and args.workload == "realistic" and not args.no_form_compare):
+        plan.close()
+        out["form_comparison"] = compare_forms(psi, spec, L, H, masks, stream)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         del psi
