@@ -331,6 +331,18 @@ int tacaw_reset(tacaw_plan_t plan);
 int tacaw_plan_export(tacaw_plan_t plan, void* h_buf, int64_t buf_bytes, int64_t* bytes_needed);
 int tacaw_plan_import(tacaw_plan_t plan, const void* h_buf, int64_t bytes);
 
+/* Union of two exported states over disjoint probe sets (Eq. 2: S of a scan is
+ * the sum over its batches), e.g. shards of the probes reduced in separate
+ * processes or on separate GPUs: the accumulators are added element-wise in
+ * FP64 (an untouched probe's entries are zero in an export), the cursors of the
+ * probes pushed in either state are kept and the dropped-frame counts added.
+ * Importing the result and finalizing gives the spectra of all those probes, up
+ * to the FP64 rounding order of the sums. Host memory only, no device call:
+ * h_a, h_b and h_out are caller-owned buffers of `bytes` bytes each (h_out may
+ * be h_a or h_b). Errors: INVALID_ARG (NULL, not a state, a probe pushed in
+ * both), SHAPE (different descriptors or sizes, or bytes not the states' size). */
+int tacaw_state_merge(const void* h_a, const void* h_b, void* h_out, int64_t bytes);
+
 /* Replace the stream used for subsequent calls. */
 int tacaw_set_stream(tacaw_plan_t plan, void* hip_stream);
 

@@ -861,28 +861,38 @@ int state_fingerprint(tacaw_plan_s* P, uint64_t* out) {
   return TACAW_OK;
 }
 
+// A device array of the state: [outer][n_probe][inner bytes] when per probe
+// (outer x n_probe x inner = bytes), else one block of bytes.
+struct StateArray {
+  void* ptr;
+  int64_t bytes;
+  bool per_probe;
+  int64_t outer, inner;
+};
+
 // the device arrays of the state, in order: S, references, mean sums, correction
 // sums, per-probe detector spectra, and the per-chunk mean's corrections,
 // references and chunk means
-std::vector<std::pair<void*, int64_t>> state_arrays(tacaw_plan_s* P) {
+std::vector<StateArray> state_arrays(tacaw_plan_s* P) {
   const int64_t nk = P->n_k, np = P->d.n_probe;
-  std::vector<std::pair<void*, int64_t>> a = {
-      {P->S, (int64_t)P->n_om * nk * 8},
-      {P->cref, np * nk * 16},
-      {P->msum, np * nk * 16},
-      {P->xs, np * kMaxCorr * nk * 16}};
-  if (P->Dp) a.push_back({P->Dp, (int64_t)P->d.n_det * np * P->n_om * 8});
+  auto pp = [&](void* ptr, int64_t outer, int64_t inner) {
+    return StateArray{ptr, outer * np * inner, true, outer, inner};
+  };
+  std::vector<StateArray> a = {
+      StateArray{P->S, (int64_t)P->n_om * nk * 8, false, 0, 0},
+      pp(P->cref, 1, nk * 16), pp(P->msum, 1, nk * 16), pp(P->xs, 1, kMaxCorr * nk * 16)};
+  if (P->Dp) a.push_back(pp(P->Dp, P->d.n_det, (int64_t)P->n_om * 8));
   if (P->pcorr) {
-    a.push_back({P->pcorr, np * kMaxCorr * nk * 8});
-    a.push_back({P->pref, np * nk * 16});
-    if (P->cmean) a.push_back({P->cmean, np * (int64_t)P->Ns * nk * 16});
+    a.push_back(pp(P->pcorr, 1, kMaxCorr * nk * 8));
+    a.push_back(pp(P->pref, 1, nk * 16));
+    if (P->cmean) a.push_back(pp(P->cmean, 1, (int64_t)P->Ns * nk * 16));
   }
   return a;
 }
 
 int64_t state_bytes(tacaw_plan_s* P) {
   int64_t b = (int64_t)sizeof(StateHeader) + (int64_t)P->d.n_probe * 8;
-  for (auto& x : state_arrays(P)) b += x.second;
+  for (auto& x : state_arrays(P)) b += x.bytes;
   return b;
 }
 
@@ -921,16 +931,74 @@ int tacaw_plan_export(tacaw_plan_t P, void* h_buf, int64_t buf_bytes, int64_t* b
   out += sizeof h;
   std::memcpy(out, P->cursor.data(), (size_t)P->d.n_probe * 8);
   out += (int64_t)P->d.n_probe * 8;
-  for (auto& x : state_arrays(P)) {
-    if (x.first == P->S && P->s_fresh) {
-      std::memset(out, 0, (size_t)x.second);  // no chunk launched since the reset
+  const auto arrays = state_arrays(P);
+  std::vector<char*> at;
+  for (auto& x : arrays) {
+    at.push_back(out);
+    if (x.ptr == P->S && P->s_fresh) {
+      std::memset(out, 0, (size_t)x.bytes);  // no chunk launched since the reset
     } else {
-      TRY(hip_check(hipMemcpyAsync(out, x.first, (size_t)x.second, hipMemcpyDeviceToHost, P->st),
+      TRY(hip_check(hipMemcpyAsync(out, x.ptr, (size_t)x.bytes, hipMemcpyDeviceToHost, P->st),
                     "state export"));
     }
-    out += x.second;
+    out += x.bytes;
   }
   TRY(hip_check(hipStreamSynchronize(P->st), "state export"));
+  // an untouched probe's entries are zero in every array (some per-probe buffers
+  // are only written when the probe runs), so that states of disjoint probe sets
+  // add up to their union
+  const int64_t np = P->d.n_probe;
+  for (size_t i = 0; i < arrays.size(); ++i) {
+    if (!arrays[i].per_probe) continue;
+    for (int64_t p = 0; p < np; ++p) {
+      if (P->cursor[(size_t)p] != 0) continue;
+      for (int64_t o = 0; o < arrays[i].outer; ++o)
+        std::memset(at[i] + (o * np + p) * arrays[i].inner, 0, (size_t)arrays[i].inner);
+    }
+  }
+  return TACAW_OK;
+}
+
+int tacaw_state_merge(const void* h_a, const void* h_b, void* h_out, int64_t bytes) {
+  g_err.clear();
+  if (!h_a || !h_b || !h_out) return fail(TACAW_ERR_INVALID_ARG, "states must not be NULL");
+  if (bytes < (int64_t)sizeof(StateHeader)) return fail(TACAW_ERR_SHAPE, "state buffer too small");
+  StateHeader ha, hb;
+  std::memcpy(&ha, h_a, sizeof ha);
+  std::memcpy(&hb, h_b, sizeof hb);
+  if (ha.magic != kStateMagic || hb.magic != kStateMagic)
+    return fail(TACAW_ERR_INVALID_ARG, "not a plan state");
+  if (ha.fingerprint != hb.fingerprint || ha.total_bytes != hb.total_bytes ||
+      ha.n_probe != hb.n_probe || ha.n_k != hb.n_k || ha.n_om != hb.n_om ||
+      ha.n_det != hb.n_det || ha.per_chunk != hb.per_chunk)
+    return fail(TACAW_ERR_SHAPE, "the states belong to plans with different descriptors");
+  if (ha.total_bytes != bytes || ha.n_probe < 1 ||
+      (int64_t)sizeof(StateHeader) + (int64_t)ha.n_probe * 8 > bytes ||
+      (bytes - (int64_t)sizeof(StateHeader) - (int64_t)ha.n_probe * 8) % 8 != 0)
+    return fail(TACAW_ERR_SHAPE, "state size does not match its header");
+  const int64_t np = ha.n_probe;
+  std::vector<int64_t> ca((size_t)np), cb((size_t)np);
+  std::memcpy(ca.data(), (const char*)h_a + sizeof ha, (size_t)np * 8);
+  std::memcpy(cb.data(), (const char*)h_b + sizeof hb, (size_t)np * 8);
+  for (int64_t p = 0; p < np; ++p)
+    if (ca[p] != 0 && cb[p] != 0)
+      return fail(TACAW_ERR_INVALID_ARG,
+                  "probe " + std::to_string(p) + " was pushed in both states");
+  // every accumulator is a sum over probes and chunks, and each probe's own entries
+  // are zero where it was not pushed: the union is the element-wise FP64 sum
+  const int64_t n = (bytes - (int64_t)sizeof(StateHeader) - np * 8) / 8;
+  const double* xa = (const double*)((const char*)h_a + sizeof ha + np * 8);
+  const double* xb = (const double*)((const char*)h_b + sizeof hb + np * 8);
+  std::vector<double> sum((size_t)n);
+  for (int64_t i = 0; i < n; ++i) sum[(size_t)i] = xa[i] + xb[i];
+  StateHeader ho = ha;
+  ho.s_defined = ha.s_defined | hb.s_defined;
+  ho.dropped = ha.dropped + hb.dropped;
+  char* out = (char*)h_out;  // may alias h_a or h_b: everything was read above
+  std::memcpy(out, &ho, sizeof ho);
+  for (int64_t p = 0; p < np; ++p) ca[p] = ca[p] != 0 ? ca[p] : cb[p];
+  std::memcpy(out + sizeof ho, ca.data(), (size_t)np * 8);
+  std::memcpy(out + sizeof ho + np * 8, sum.data(), (size_t)n * 8);
   return TACAW_OK;
 }
 
@@ -960,9 +1028,9 @@ int tacaw_plan_import(tacaw_plan_t P, const void* h_buf, int64_t bytes) {
     if (c < 0 || (c != 0 && c < P->n_used) || c > P->d.n_frames)
       return fail(TACAW_ERR_INVALID_ARG, "state holds a probe cursor off a probe boundary");
   for (auto& x : state_arrays(P)) {
-    TRY(hip_check(hipMemcpyAsync(x.first, in, (size_t)x.second, hipMemcpyHostToDevice, P->st),
+    TRY(hip_check(hipMemcpyAsync(x.ptr, in, (size_t)x.bytes, hipMemcpyHostToDevice, P->st),
                   "state import"));
-    in += x.second;
+    in += x.bytes;
   }
   TRY(hip_check(hipStreamSynchronize(P->st), "state import"));
   for (int p = 0; p < P->d.n_probe; ++p) {

@@ -98,6 +98,7 @@ def _load():
         "tacaw_reset": (C.c_int, [P]),
         "tacaw_plan_export": (C.c_int, [P, P, C.c_int64, C.POINTER(C.c_int64)]),
         "tacaw_plan_import": (C.c_int, [P, P, C.c_int64]),
+        "tacaw_state_merge": (C.c_int, [P, P, P, C.c_int64]),
         "tacaw_set_stream": (C.c_int, [P, P]),
         "tacaw_plan_get_info": (C.c_int, [P, C.POINTER(PlanInfo)]),
         "tacaw_destroy": (None, [P]),
@@ -117,7 +118,7 @@ lib = _load()
 EXPORTED = ("tacaw_plan", "tacaw_plan_check", "tacaw_push_frames", "tacaw_ingest_frames",
             "tacaw_commit_frames", "tacaw_ingest_frames_tiled", "tacaw_finalize",
             "tacaw_detector_spectra", "tacaw_backward", "tacaw_backward_static", "tacaw_reset",
-            "tacaw_set_stream", "tacaw_plan_export", "tacaw_plan_import",
+            "tacaw_set_stream", "tacaw_plan_export", "tacaw_plan_import", "tacaw_state_merge",
             "tacaw_plan_get_info", "tacaw_destroy", "tacaw_last_error", "tacaw_version",
             "tacaw_read_probe", "tacaw_read_probe_columns", "tacaw_synth_frames")
 
@@ -153,6 +154,15 @@ def make_desc(n_probe, ny, nx, n_frames, seg_len, hop, window="hann", window_par
                  int(ring_frames), int(k_row_stride), int(omega_half))
     d._window_values = window_values  # keep the host array alive with the descriptor
     return d
+
+
+def merge_states(a: bytes, b: bytes) -> bytes:
+    """Union of two exported plan states over disjoint probe sets (host only)."""
+    if len(a) != len(b):
+        raise TacawError(-2, "states of different sizes")
+    out = C.create_string_buffer(len(a))
+    _check(lib.tacaw_state_merge(a, b, out, len(a)))
+    return out.raw
 
 
 def check_desc(**kw) -> None:

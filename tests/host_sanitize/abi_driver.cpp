@@ -7,6 +7,7 @@
 // Exit status 0 when every call returned what is expected; the sanitizers report
 // memory and undefined-behaviour errors themselves.
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -292,6 +293,46 @@ int main() {
          "export NULL", 0);
   expect(tacaw_plan_import(nullptr, state, sizeof state) == TACAW_ERR_INVALID_ARG, "import NULL",
          0);
+
+  // ---- state merge (host only), on forged states with the exported layout ----
+  {
+    struct Head {  // format tag, fingerprint, size, probes, pixels, bins, detectors,
+      uint64_t magic, fp;  // per-chunk flag, S defined, frames dropped
+      int64_t total;
+      int32_t np, nk, nom, ndet, pc, sdef;
+      int64_t dropped;
+    };
+    const int np = 3, nb = 20;
+    const int64_t bytes = (int64_t)sizeof(Head) + np * 8 + nb * 8;
+    std::vector<unsigned char> sa((size_t)bytes), sb((size_t)bytes), so((size_t)bytes);
+    auto fill = [&](std::vector<unsigned char>& v, int64_t c0, int64_t c1, int64_t c2, double x) {
+      const Head h{0x31305354574154ull, 7, bytes, np, 4, 5, 1, 0, 1, 3};
+      std::memcpy(v.data(), &h, sizeof h);
+      const int64_t c[3] = {c0, c1, c2};
+      std::memcpy(v.data() + sizeof h, c, sizeof c);
+      for (int i = 0; i < nb; ++i) {
+        const double d = x + i;
+        std::memcpy(v.data() + sizeof h + np * 8 + i * 8, &d, 8);
+      }
+    };
+    fill(sa, 9, 0, 0, 1.0);
+    fill(sb, 0, 9, 9, 2.0);
+    int rc = tacaw_state_merge(sa.data(), sb.data(), so.data(), bytes);
+    expect(rc == TACAW_OK, "merge", rc);
+    double last = 0.0;
+    std::memcpy(&last, so.data() + bytes - 8, 8);
+    expect(last == 1.0 + 19 + 2.0 + 19, "merge sum", 0);
+    rc = tacaw_state_merge(sa.data(), sb.data(), sa.data(), bytes);
+    expect(rc == TACAW_OK, "merge in place", rc);
+    rc = tacaw_state_merge(sa.data(), sb.data(), so.data(), bytes);  // now overlapping
+    expect(rc == TACAW_ERR_INVALID_ARG, "merge overlap", rc);
+    rc = tacaw_state_merge(sb.data(), sb.data(), so.data(), bytes - 8);
+    expect(rc == TACAW_ERR_SHAPE, "merge size", rc);
+    rc = tacaw_state_merge(sb.data(), sb.data(), so.data(), 16);
+    expect(rc == TACAW_ERR_SHAPE, "merge short", rc);
+    rc = tacaw_state_merge(nullptr, sb.data(), so.data(), bytes);
+    expect(rc == TACAW_ERR_INVALID_ARG, "merge NULL", rc);
+  }
   tacaw_destroy(nullptr);
 
   // ---- producer and read probes: argument checks ----

@@ -11,7 +11,8 @@ FFT and both GEMM forms, the per-chunk mean, the deferred ring, complex128 input
 with an energy window and probe sums, a state taken before any push, and probes
 completed out of order; the uninterrupted run itself is checked against the FP64
 oracle once. The refusals (mid-probe export, import into a used plan or one with
-another descriptor or masks, truncated or foreign bytes) are checked too."""
+another descriptor or masks, truncated or foreign bytes) are checked too, and the
+union of states exported by plans that each reduced one shard of the probes."""
 
 import numpy as np
 import pytest
@@ -187,3 +188,34 @@ def test_export_and_import_refusals(tacaw):
     fresh.import_state(good)
     assert fresh.info()["probes_complete"] == 1
     fresh.close()
+
+
+@pytest.mark.parametrize("case", ["fft", "per_chunk_mean", "gemm_bf16x3", "c128_window_sum"])
+def test_union_of_probe_shards(tacaw, case):
+    # two shards of the probes reduced by separate plans (as separate processes or
+    # GPUs would), their states merged on the host, imported and finalized: the
+    # spectra of one run over all probes, up to the FP64 order of the shard sums
+    kw, piece = CASES[case]["kw"], CASES[case]["piece"]
+    x = series(kw.get("in_dtype", "c64"), seed=21).cuda()
+    m = masks()
+    print(f"probe shards, case {case}", flush=True)
+    ref = tacaw.Plan(P, NY, NX, NT, L, H, masks=m, **kw)
+    push_group(ref, x, 0, 2, piece)
+    push_group(ref, x, 2, 2, piece)
+    want = results(ref)
+
+    states = []
+    for p0 in (0, 2):
+        shard = tacaw.Plan(P, NY, NX, NT, L, H, masks=m, **kw)
+        push_group(shard, x, p0, 2, piece)
+        states.append(shard.export_state())
+        shard.close()
+    merged = tacaw.merge_states(*states)
+    final = tacaw.Plan(P, NY, NX, NT, L, H, masks=m, **kw)
+    final.import_state(merged)
+    got = results(final)
+    for k in ("S", "D", "Dp"):
+        e = np.linalg.norm((got[k] - want[k]).ravel()) / np.linalg.norm(want[k].ravel())
+        assert e <= 1e-12, f"{case}: {k} differs by {e:.2e}"
+    for k in ("frames_dropped", "probes_complete"):
+        assert got["info"][k] == want["info"][k]
