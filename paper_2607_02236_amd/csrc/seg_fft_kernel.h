@@ -353,6 +353,11 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
       using C2 = std::integral_constant<int, 2>;
       using C3 = std::integral_constant<int, 3>;
 
+      // the thread's window values, read before the samples are taken
+      float wv[N1];
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) wv[n1] = s_win[n2 * N1 + n1];
+      __builtin_amdgcn_sched_barrier(0);
       if constexpr (LEAN) {
         // H = L/2, chunk s: frames with t >= L/2 (n1 >= HALF) are new; t < L/2 are new
         // only for s = 0. H = L: every frame of every chunk is new.
@@ -417,14 +422,18 @@ __global__ void __launch_bounds__(FftShape<L>::W*(L / FftShape<L>::N1))
       // window (table stored per thread: s_win[n2 * N1 + n1] = w(N2 n1 + n2))
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) {
-        const float w = s_win[n2 * N1 + n1];
-        v[n1].x *= w;
-        v[n1].y *= w;
+        v[n1].x *= wv[n1];
+        v[n1].y *= wv[n1];
       }
-      // pass 1: DFT over n1, then twiddle exp(-2 pi i n2 k1 / L)
+      // pass 1: DFT over n1, then twiddle exp(-2 pi i n2 k1 / L); the twiddles are
+      // read first, so that their LDS latency passes during the DFT
+      float2 twv[N1];
+#pragma unroll
+      for (int k1 = 1; k1 < N1; ++k1) twv[k1] = s_tw[n2 * N1 + k1];
+      __builtin_amdgcn_sched_barrier(0);
       dft_inplace<N1>(v);
 #pragma unroll
-      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], s_tw[n2 * N1 + k1]);
+      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], twv[k1]);
 
       // tile (cc & 1), cc counting this thread block's chunks: the reads of
       // chunk cc - 2 from it finished before the barrier of chunk cc - 1, so only

@@ -251,10 +251,15 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
             pre[n1] = buffer_load<InT>(group(a.in, ii, ss, n1), group_bytes, lane_off);
         }
       }
-      // ---- forward transform: time layout -> bin layout X[t] = X(bin(t))
+      // ---- forward transform: time layout -> bin layout X[t] = X(bin(t)); the
+      // twiddles are read first, so that their LDS latency passes during the DFT
+      float2 twv[N1];
+#pragma unroll
+      for (int k1 = 1; k1 < N1; ++k1) twv[k1] = s_tw[n2 * N1 + k1];
+      __builtin_amdgcn_sched_barrier(0);
       dft_inplace<N1>(v);
 #pragma unroll
-      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], s_tw[n2 * N1 + k1]);
+      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], twv[k1]);
 #pragma unroll
       for (int k1 = 0; k1 < N1; ++k1) xa[k1 * KROW + n2 * W + px] = v[k1];
       __syncthreads();  // (1) forward tile written; the inverse tile's reads of the previous chunk are done
@@ -345,7 +350,7 @@ __global__ void __launch_bounds__(BwdShape<L>::W*(L / BwdShape<L>::N1))
         }
       }
 #pragma unroll
-      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], s_tw[n2 * N1 + k1]);
+      for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], twv[k1]);
       dft_inplace<N1>(v);  // v[n1] = conj(g_y(N2 n1 + n2)) / 2
       float2 msub = make_float2(0.f, 0.f);  // MT 3: M_s / L
       if constexpr (MT == 3) {
