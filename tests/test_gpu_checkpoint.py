@@ -7,7 +7,8 @@ remaining chunk launches add the same values in the same order and S is bitwise
 equal. The detector sums D and D_p are FP64 atomic sums over pixel tiles, whose
 order varies from run to run even without a checkpoint: they agree to a few
 FP64 roundings (relative 1e-12). Covered for the
-FFT and both GEMM forms, the per-chunk mean, the deferred ring, complex128 input
+FFT and both GEMM forms, the per-chunk mean, the deferred ring (per frame and per
+pixel tile), complex128 input
 with an energy window and probe sums, a state taken before any push, and probes
 completed out of order; the uninterrupted run itself is checked against the FP64
 oracle once. The refusals (mid-probe export, import into a used plan or one with
@@ -73,6 +74,7 @@ CASES = {
     "fft": dict(kw={}, piece=300),
     "per_chunk_mean": dict(kw={"mean_mode": "per_segment"}, piece=300),
     "deferred_ring": dict(kw={"ring_frames": 512}, piece=200),
+    "tiled_ring": dict(kw={"ring_frames": 512, "tiled_ring": True}, piece=200),
     "gemm_bf16x3": dict(kw={"transform": "gemm_bf16x3"}, piece=300),
     "gemm_f16x3": dict(kw={"transform": "gemm_f16x3"}, piece=NT),
     "c128_window_sum": dict(kw={"in_dtype": "c128", "omega_half": 40, "probe_reduce": "sum"},
