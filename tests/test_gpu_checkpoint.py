@@ -221,3 +221,38 @@ def test_union_of_probe_shards(tacaw, case):
         assert e <= 1e-12, f"{case}: {k} differs by {e:.2e}"
     for k in ("frames_dropped", "probes_complete"):
         assert got["info"][k] == want["info"][k]
+
+
+def test_resume_and_merge_without_masks(tacaw):
+    # a plan with no detector masks has no per-probe detector spectra in its state
+    x = series(seed=31).cuda()
+    ref = tacaw.Plan(P, NY, NX, NT, L, H)
+    push_group(ref, x, 0, 2, 300)
+    push_group(ref, x, 2, 2, 300)
+    want = ref.finalize().cpu().numpy()
+    ref.close()
+    shards = []
+    for p0 in (0, 2):
+        sh = tacaw.Plan(P, NY, NX, NT, L, H)
+        push_group(sh, x, p0, 2, 300)
+        shards.append(sh.export_state())
+        sh.close()
+    for state, label in ((shards[0], "resume"), (tacaw.merge_states(*shards), "merge")):
+        plan = tacaw.Plan(P, NY, NX, NT, L, H)
+        plan.import_state(state)
+        if label == "resume":
+            push_group(plan, x, 2, 2, 300)
+            assert np.array_equal(plan.finalize().cpu().numpy(), want)
+        else:
+            got = plan.finalize().cpu().numpy()
+            assert np.linalg.norm(got - want) / np.linalg.norm(want) <= 1e-12
+        plan.close()
+    # a state with masks does not load into a plan without them
+    with_masks = tacaw.Plan(P, NY, NX, NT, L, H, masks=masks())
+    other = with_masks.export_state()
+    with_masks.close()
+    plan = tacaw.Plan(P, NY, NX, NT, L, H)
+    with pytest.raises(tacaw.TacawError) as e:
+        plan.import_state(other)
+    assert e.value.kind == "SHAPE"
+    plan.close()
